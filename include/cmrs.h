@@ -1,0 +1,192 @@
+/*
+ * cmrs.h -- C ABI of libcmrs.so: Compressed Multi-Row Storage (CMRS) sparse
+ * matrices and their matrix-vector product on AMD MI355X (gfx950).
+ *
+ * Method: Z. Koza, M. Matyka, S. Szkoda, L. Miroslaw, "Compressed Multi-Row
+ * Storage Format for Sparse Matrices on Graphics Processing Units",
+ * arXiv:1203.2946.
+ *
+ * Conventions for every call below
+ *   - All array pointers are DEVICE pointers (hipMalloc'd or equivalent),
+ *     unless marked "host".  Indices are zero-based int32.
+ *   - Every call that takes a stream is stream-ordered and asynchronous: it
+ *     validates its host-side arguments, enqueues kernels on `stream` and
+ *     returns.  Results are visible after the stream is synchronised.
+ *   - The library allocates no device memory.  Every buffer, including the
+ *     workspaces sized by the *_workspace queries, belongs to the caller and
+ *     must stay alive until the enqueued work has finished.
+ *   - Every call returns a cmrs_status_t and never throws.  Host-side
+ *     argument checks happen before anything is enqueued (nothing is written
+ *     on error).  A HIP launch error maps to CMRS_ERR_DEVICE with details in
+ *     cmrs_last_error().
+ *   - Data-dependent validity of a CSR input (row_ptr[0] == 0, monotone
+ *     row_ptr, row_ptr[rows] == nnz, 0 <= col < cols) is NOT checked on the
+ *     hot path; cmrs_validate_csr() checks it on the device.  Invalid data
+ *     gives unspecified results but never out-of-bounds accesses of the
+ *     arrays whose sizes the call was given, except through invalid indices.
+ */
+#ifndef CMRS_H_
+#define CMRS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CMRS_ABI_VERSION 1
+
+typedef enum {
+    CMRS_OK = 0,
+    CMRS_ERR_INVALID_VALUE = 1,   /* bad size, height, pointer, dtype or flag   */
+    CMRS_ERR_INDEX_OVERFLOW = 2,  /* cols does not fit the packed column field  */
+    CMRS_ERR_NOT_SUPPORTED = 3,   /* valid request that this build cannot serve */
+    CMRS_ERR_DEVICE = 4,          /* HIP error while enqueueing                 */
+    CMRS_ERR_WORKSPACE = 5        /* workspace pointer NULL or too small        */
+} cmrs_status_t;
+
+typedef enum {
+    CMRS_R64F = 0,   /* IEEE binary64 */
+    CMRS_R32F = 1,   /* IEEE binary32 */
+    CMRS_R16BF = 2   /* bfloat16 (8 significant bits, fp32 exponent range) */
+} cmrs_dtype_t;
+
+/* Conversion flag: reorder the entries of every strip by column, ties by
+ * RowInStrip, exact duplicates kept in CSR order (Sec. 4, fourth
+ * optimisation; the worked height-2 example of that section fixes the tie
+ * order). */
+#define CMRS_SORT 1u
+
+/* Largest supported strip height. */
+#define CMRS_MAX_HEIGHT 32
+
+/* SpMV kernel variants (cmrs_spmv `variant`). */
+#define CMRS_SPMV_AUTO 0   /* library's choice for (height, dtype)                  */
+#define CMRS_SPMV_LDS 1    /* one wave64 per strip, per-lane partial sums in LDS     */
+#define CMRS_SPMV_REG 2    /* one wave64 per strip, per-lane partial sums in VGPRs   */
+
+/*
+ * A CMRS matrix (Sec. 3): `height` rows per strip, strips = ceil(rows/height).
+ *   strip_ptr[strips+1]: strip_ptr[j] is the index of the first entry of strip
+ *       j, strip_ptr[strips] = nnz; strip j holds rows j*height .. j*height +
+ *       height - 1 (the last strip may be partial).
+ *   col_word[nnz]: packed (column << bits) | RowInStrip, with RowInStrip = row
+ *       mod height (Sec. 4 packs the two into one 32-bit word; bits =
+ *       cmrs_bits_for_height(height)).  Unsigned: the column field holds
+ *       32 - bits bits.
+ *   val[nnz]: the matrix values in `val_dtype`, in the same order.
+ * `sorted` records whether the strips were reordered (CMRS_SORT); the SpMV is
+ * correct for any order of entries inside a strip.
+ * This struct is a host-side, non-owning view; the library keeps no
+ * reference to it after a call returns.
+ */
+typedef struct {
+    int32_t rows;
+    int32_t cols;
+    int32_t nnz;
+    int32_t height;
+    int32_t bits;
+    int32_t sorted;
+    cmrs_dtype_t val_dtype;
+    const int32_t *strip_ptr;
+    const uint32_t *col_word;
+    const void *val;
+} cmrs_mat_t;
+
+/* ABI version of the loaded library (CMRS_ABI_VERSION it was built with). */
+int32_t cmrs_abi_version(void);
+
+/* ceil(rows / height) (Sec. 3); -1 if rows < 0 or height < 1.  Host only. */
+int32_t cmrs_num_strips(int32_t rows, int32_t height);
+
+/* Width of the packed RowInStrip field: max(4, ceil(log2(height))).  Sec. 4
+ * uses 4 bits (heights up to 16); height 17..32 needs 5.  -1 if height is
+ * outside [1, CMRS_MAX_HEIGHT].  Host only. */
+int32_t cmrs_bits_for_height(int32_t height);
+
+/* Bytes of workspace cmrs_from_csr needs: 0 without CMRS_SORT; with it,
+ * room for the strips that do not fit one workgroup's LDS (a list of their
+ * indices and a global sort buffer).  Host only. */
+size_t cmrs_from_csr_workspace(int32_t rows, int32_t nnz, int32_t height, uint32_t flags);
+
+/*
+ * CSR -> CMRS (Sec. 3: strip_ptr[j] = row_ptr[j*height], strip_ptr[strips] =
+ * nnz, RowInStrip = row mod height; Sec. 4: packed words; with CMRS_SORT the
+ * in-strip reorder of Sec. 4).
+ *   rows, cols, nnz   matrix sizes (>= 0); cols <= 2^(32 - bits) else
+ *                     CMRS_ERR_INDEX_OVERFLOW.
+ *   row_ptr[rows+1], col_ind[nnz], val_in[nnz]   CSR input (device).
+ *   dtype             element type of val_in / val_out.
+ *   height            1 .. CMRS_MAX_HEIGHT.
+ *   flags             0 or CMRS_SORT.
+ *   strip_ptr_out[strips+1], col_word_out[nnz], val_out[nnz]   CMRS output.
+ *   workspace / workspace_bytes  >= cmrs_from_csr_workspace(...) bytes
+ *                     (may be NULL when that is 0).
+ * Aliasing: without CMRS_SORT, col_word_out may equal col_ind (in-place
+ * packing) and val_out may equal val_in (the values are then not touched);
+ * the paper's conversion is in place (Sec. 7).  With CMRS_SORT no output may
+ * overlap an input.
+ */
+cmrs_status_t cmrs_from_csr(int32_t rows, int32_t cols, int32_t nnz,
+                            const int32_t *row_ptr, const int32_t *col_ind, const void *val_in,
+                            cmrs_dtype_t dtype, int32_t height, uint32_t flags,
+                            int32_t *strip_ptr_out, uint32_t *col_word_out, void *val_out,
+                            void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Bytes of workspace cmrs_to_csr needs (currently always 0).  Host only. */
+size_t cmrs_to_csr_workspace(const cmrs_mat_t *A);
+
+/*
+ * CMRS -> CSR, the inverse conversion (Sec. 3; Sec. 7 calls it quick and in
+ * place).  Row s*height + r of strip s collects, in the order they appear in
+ * the strip, the entries whose RowInStrip is r; column = word >> bits.
+ *   row_ptr_out[rows+1], col_ind_out[nnz], val_out[nnz]   CSR output (device);
+ *   no output may overlap an input.
+ * For an unsorted CMRS matrix this reproduces the CSR it came from bit for
+ * bit; for a sorted one, columns come out ascending inside each row.
+ */
+cmrs_status_t cmrs_to_csr(const cmrs_mat_t *A, int32_t *row_ptr_out, int32_t *col_ind_out,
+                          void *val_out, void *workspace, size_t workspace_bytes,
+                          hipStream_t stream);
+
+/*
+ * y = A x (Sec. 2.1), Algorithm 1 of Sec. 4: every strip is processed by one
+ * 64-lane wave; lane l takes entries start+l, start+l+64, ..., adds
+ * Val[j] * x[col] into its own partial sum for row RowInStrip; the partials
+ * are then reduced across lanes and the wave writes the strip's `height`
+ * results.
+ *   x[cols], y[rows]  device vectors of xy_dtype; must not overlap.
+ *   xy_dtype          R64F with R64F values (fp64 arithmetic), R32F with R32F
+ *                     values (fp32 arithmetic), or R32F with R16BF values
+ *                     (values widened to fp32, fp32 arithmetic).
+ *   variant           CMRS_SPMV_* (AUTO picks per height and dtype).
+ * y is overwritten (Algorithm 1 assigns the row sums): rows without entries
+ * get +0.0.  rows == 0 is a no-op.  Deterministic: the same inputs give the
+ * same bits on every call.
+ */
+cmrs_status_t cmrs_spmv(const cmrs_mat_t *A, const void *x, void *y, cmrs_dtype_t xy_dtype,
+                        int32_t variant, hipStream_t stream);
+
+/*
+ * Device check of CSR validity: writes *flag_out = 0 when row_ptr[0] == 0,
+ * row_ptr is non-decreasing, row_ptr[rows] == nnz and every column is in
+ * [0, cols); otherwise a non-zero bit mask (1: row_ptr[0] or row_ptr[rows]
+ * wrong, 2: row_ptr decreasing, 4: column out of range).  flag_out is one
+ * device int32.
+ */
+cmrs_status_t cmrs_validate_csr(int32_t rows, int32_t cols, int32_t nnz, const int32_t *row_ptr,
+                                const int32_t *col_ind, int32_t *flag_out, hipStream_t stream);
+
+/* Static string for a status code. */
+const char *cmrs_status_string(cmrs_status_t s);
+
+/* Detail of the last error on the calling host thread ("" if none). */
+const char *cmrs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CMRS_H_ */

@@ -1,0 +1,231 @@
+"""Python binding of libcmrs.so (argument marshalling only).
+
+Every computation runs in the library's HIP kernels; this module checks
+tensor devices, dtypes and contiguity, allocates outputs and workspaces with
+torch, and passes raw device pointers plus torch's current HIP stream through
+the C ABI declared in include/cmrs.h.  Importing it fails loudly when the
+library is not built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcmrs.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_1203_2946_amd.build` "
+                      "(or __graft_entry__.build()) first")
+lib = ctypes.CDLL(LIB_PATH)
+
+# ----------------------------------------------------------------- C ABI
+CMRS_OK = 0
+CMRS_ERR_INVALID_VALUE = 1
+CMRS_ERR_INDEX_OVERFLOW = 2
+CMRS_ERR_NOT_SUPPORTED = 3
+CMRS_ERR_DEVICE = 4
+CMRS_ERR_WORKSPACE = 5
+
+CMRS_R64F, CMRS_R32F, CMRS_R16BF = 0, 1, 2
+CMRS_SORT = 1
+CMRS_MAX_HEIGHT = 32
+SPMV_AUTO, SPMV_LDS, SPMV_REG = 0, 1, 2
+VARIANTS = {"auto": SPMV_AUTO, "lds": SPMV_LDS, "reg": SPMV_REG}
+
+_DT = {torch.float64: CMRS_R64F, torch.float32: CMRS_R32F, torch.bfloat16: CMRS_R16BF}
+
+
+class CmrsMatDesc(ctypes.Structure):
+    _fields_ = [
+        ("rows", ctypes.c_int32), ("cols", ctypes.c_int32), ("nnz", ctypes.c_int32),
+        ("height", ctypes.c_int32), ("bits", ctypes.c_int32), ("sorted", ctypes.c_int32),
+        ("val_dtype", ctypes.c_int), ("strip_ptr", ctypes.c_void_p), ("col_word", ctypes.c_void_p),
+        ("val", ctypes.c_void_p),
+    ]
+
+
+_i32, _u32, _sz, _vp = ctypes.c_int32, ctypes.c_uint32, ctypes.c_size_t, ctypes.c_void_p
+_DP = ctypes.POINTER(CmrsMatDesc)
+lib.cmrs_abi_version.argtypes, lib.cmrs_abi_version.restype = [], _i32
+lib.cmrs_num_strips.argtypes, lib.cmrs_num_strips.restype = [_i32, _i32], _i32
+lib.cmrs_bits_for_height.argtypes, lib.cmrs_bits_for_height.restype = [_i32], _i32
+lib.cmrs_from_csr_workspace.argtypes, lib.cmrs_from_csr_workspace.restype = [_i32, _i32, _i32, _u32], _sz
+lib.cmrs_from_csr.argtypes = [_i32, _i32, _i32, _vp, _vp, _vp, ctypes.c_int, _i32, _u32, _vp, _vp, _vp, _vp, _sz, _vp]
+lib.cmrs_from_csr.restype = ctypes.c_int
+lib.cmrs_to_csr_workspace.argtypes, lib.cmrs_to_csr_workspace.restype = [_DP], _sz
+lib.cmrs_to_csr.argtypes = [_DP, _vp, _vp, _vp, _vp, _sz, _vp]
+lib.cmrs_to_csr.restype = ctypes.c_int
+lib.cmrs_spmv.argtypes = [_DP, _vp, _vp, ctypes.c_int, _i32, _vp]
+lib.cmrs_spmv.restype = ctypes.c_int
+lib.cmrs_validate_csr.argtypes = [_i32, _i32, _i32, _vp, _vp, _vp, _vp]
+lib.cmrs_validate_csr.restype = ctypes.c_int
+lib.cmrs_status_string.argtypes, lib.cmrs_status_string.restype = [ctypes.c_int], ctypes.c_char_p
+lib.cmrs_last_error.argtypes, lib.cmrs_last_error.restype = [], ctypes.c_char_p
+
+EXPORTED = ["cmrs_abi_version", "cmrs_num_strips", "cmrs_bits_for_height", "cmrs_from_csr_workspace",
+            "cmrs_from_csr", "cmrs_to_csr_workspace", "cmrs_to_csr", "cmrs_spmv", "cmrs_validate_csr",
+            "cmrs_status_string", "cmrs_last_error"]
+
+
+class CmrsError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        name = lib.cmrs_status_string(status).decode()
+        detail = lib.cmrs_last_error().decode()
+        super().__init__(f"{where}: {name}: {detail}")
+
+
+def _check(status: int, where: str):
+    if status != CMRS_OK:
+        raise CmrsError(status, where)
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    if t is None or t.numel() == 0:
+        return None
+    return t.data_ptr()
+
+
+def _dev(t: torch.Tensor, name: str, dtype=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    return t
+
+
+# ----------------------------------------------------------------- API
+def abi_version() -> int:
+    return int(lib.cmrs_abi_version())
+
+
+def num_strips(rows: int, height: int) -> int:
+    return int(lib.cmrs_num_strips(rows, height))
+
+
+def bits_for_height(height: int) -> int:
+    return int(lib.cmrs_bits_for_height(height))
+
+
+@dataclass
+class CmrsMatrix:
+    """A CMRS matrix on the GPU: strip_ptr int32[strips+1], col_word int32
+    [nnz] holding the uint32 packed words, val [nnz]."""
+    rows: int
+    cols: int
+    height: int
+    bits: int
+    sorted: bool
+    strip_ptr: torch.Tensor
+    col_word: torch.Tensor
+    val: torch.Tensor
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col_word.numel())
+
+    @property
+    def strips(self) -> int:
+        return int(self.strip_ptr.numel()) - 1
+
+    def desc(self) -> CmrsMatDesc:
+        return CmrsMatDesc(self.rows, self.cols, self.nnz, self.height, self.bits, int(self.sorted),
+                           _DT[self.val.dtype], _ptr(self.strip_ptr), _ptr(self.col_word), _ptr(self.val))
+
+
+def from_csr_workspace_bytes(rows: int, nnz: int, height: int, sort: bool) -> int:
+    return int(lib.cmrs_from_csr_workspace(rows, nnz, height, CMRS_SORT if sort else 0))
+
+
+def from_csr(row_ptr: torch.Tensor, col_ind: torch.Tensor, val: torch.Tensor, cols: int, height: int,
+             sort: bool = False, in_place: bool = False, workspace: torch.Tensor | None = None,
+             out: CmrsMatrix | None = None, stream=None) -> CmrsMatrix:
+    """CSR -> CMRS on the GPU.  in_place (unsorted only) packs the column words
+    into col_ind's storage and keeps val's storage.  ``out`` reuses the arrays
+    of an existing matrix of the same shape."""
+    _dev(row_ptr, "row_ptr", torch.int32)
+    _dev(col_ind, "col_ind", torch.int32)
+    _dev(val, "val")
+    if val.dtype not in _DT:
+        raise TypeError(f"unsupported value dtype {val.dtype}")
+    rows = row_ptr.numel() - 1
+    nnz = col_ind.numel()
+    if val.numel() != nnz:
+        raise ValueError("val and col_ind differ in length")
+    if in_place and sort:
+        raise ValueError("the sorted conversion cannot run in place")
+    strips = num_strips(rows, height)
+    if strips < 0 or bits_for_height(height) < 0:
+        raise ValueError(f"bad height {height}")
+    dev = row_ptr.device
+    if out is not None:
+        sp, cw, vo = out.strip_ptr, out.col_word, out.val
+    else:
+        sp = torch.empty(strips + 1, dtype=torch.int32, device=dev)
+        cw = col_ind if in_place else torch.empty(nnz, dtype=torch.int32, device=dev)
+        vo = val if in_place else torch.empty_like(val)
+    wsb = from_csr_workspace_bytes(rows, nnz, height, sort)
+    if wsb and (workspace is None or workspace.numel() * workspace.element_size() < wsb):
+        workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    st = lib.cmrs_from_csr(rows, cols, nnz, _ptr(row_ptr), _ptr(col_ind), _ptr(val), _DT[val.dtype], height,
+                           CMRS_SORT if sort else 0, _ptr(sp), _ptr(cw), _ptr(vo),
+                           _ptr(workspace) if wsb else None, wsb, _stream(stream))
+    _check(st, "cmrs_from_csr")
+    return CmrsMatrix(rows, cols, height, bits_for_height(height), bool(sort), sp, cw, vo)
+
+
+def to_csr(A: CmrsMatrix, out=None, stream=None):
+    """CMRS -> CSR on the GPU; returns (row_ptr, col_ind, val)."""
+    dev = A.col_word.device
+    if out is None:
+        rp = torch.empty(A.rows + 1, dtype=torch.int32, device=dev)
+        ci = torch.empty(A.nnz, dtype=torch.int32, device=dev)
+        vo = torch.empty_like(A.val)
+    else:
+        rp, ci, vo = out
+    d = A.desc()
+    st = lib.cmrs_to_csr(ctypes.byref(d), _ptr(rp), _ptr(ci), _ptr(vo), None, 0, _stream(stream))
+    _check(st, "cmrs_to_csr")
+    return rp, ci, vo
+
+
+def spmv(A: CmrsMatrix, x: torch.Tensor, out: torch.Tensor | None = None, variant: int | str = SPMV_AUTO,
+         stream=None) -> torch.Tensor:
+    """y = A x.  fp64 values take fp64 x/y; fp32 and bf16 values take fp32 x/y."""
+    if isinstance(variant, str):
+        variant = VARIANTS[variant]
+    xdt = torch.float64 if A.val.dtype == torch.float64 else torch.float32
+    _dev(x, "x", xdt)
+    if x.numel() != A.cols:
+        raise ValueError(f"x has {x.numel()} entries, the matrix {A.cols} columns")
+    y = out if out is not None else torch.empty(A.rows, dtype=xdt, device=x.device)
+    _dev(y, "y", xdt)
+    if y.numel() != A.rows:
+        raise ValueError("y has the wrong length")
+    d = A.desc()
+    st = lib.cmrs_spmv(ctypes.byref(d), _ptr(x), _ptr(y), _DT[xdt], int(variant), _stream(stream))
+    _check(st, "cmrs_spmv")
+    return y
+
+
+def validate_csr(row_ptr: torch.Tensor, col_ind: torch.Tensor, cols: int, stream=None) -> int:
+    """Device CSR check; returns the flag (0 = valid).  Synchronises the stream."""
+    _dev(row_ptr, "row_ptr", torch.int32)
+    _dev(col_ind, "col_ind", torch.int32)
+    flag = torch.empty(1, dtype=torch.int32, device=row_ptr.device)
+    st = lib.cmrs_validate_csr(row_ptr.numel() - 1, cols, col_ind.numel(), _ptr(row_ptr), _ptr(col_ind),
+                               flag.data_ptr(), _stream(stream))
+    _check(st, "cmrs_validate_csr")
+    return int(flag.item())

@@ -1,0 +1,191 @@
+// Host side of the C ABI declared in include/cmrs.h: argument validation,
+// error reporting and dispatch to the kernels.  Nothing here allocates.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "cmrs_internal.hpp"
+
+namespace {
+
+thread_local char g_last_error[512] = {0};
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+    va_end(ap);
+}
+
+cmrs_status_t fail(cmrs_status_t st, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+cmrs_status_t from_hip(hipError_t e, const char* where) {
+    if (e == hipSuccess) return CMRS_OK;
+    set_error("%s: %s (%s)", where, hipGetErrorName(e), hipGetErrorString(e));
+    return CMRS_ERR_DEVICE;
+}
+
+bool valid_dtype(cmrs_dtype_t t) { return t == CMRS_R64F || t == CMRS_R32F || t == CMRS_R16BF; }
+
+// Column field width check: cols must fit in 32 - bits bits.
+bool cols_fit(int32_t cols, int32_t bits) {
+    return static_cast<uint64_t>(cols) <= (static_cast<uint64_t>(1) << (32 - bits));
+}
+
+bool ranges_overlap(const void* a, size_t an, const void* b, size_t bn) {
+    if (!a || !b || an == 0 || bn == 0) return false;
+    const char* pa = static_cast<const char*>(a);
+    const char* pb = static_cast<const char*>(b);
+    return pa < pb + bn && pb < pa + an;
+}
+
+cmrs_status_t check_mat(const cmrs_mat_t* A) {
+    if (!A) return fail(CMRS_ERR_INVALID_VALUE, "matrix descriptor is NULL");
+    if (A->rows < 0 || A->cols < 0 || A->nnz < 0)
+        return fail(CMRS_ERR_INVALID_VALUE, "negative size (rows=%d cols=%d nnz=%d)", A->rows, A->cols, A->nnz);
+    if (A->height < 1 || A->height > CMRS_MAX_HEIGHT)
+        return fail(CMRS_ERR_INVALID_VALUE, "height %d outside [1, %d]", A->height, CMRS_MAX_HEIGHT);
+    if (A->bits != cmrs_bits_for_height(A->height))
+        return fail(CMRS_ERR_INVALID_VALUE, "bits %d != cmrs_bits_for_height(%d) = %d", A->bits, A->height,
+                    cmrs_bits_for_height(A->height));
+    if (!valid_dtype(A->val_dtype)) return fail(CMRS_ERR_INVALID_VALUE, "unknown value dtype %d", (int)A->val_dtype);
+    if (!cols_fit(A->cols, A->bits))
+        return fail(CMRS_ERR_INDEX_OVERFLOW, "cols=%d does not fit %d column bits", A->cols, 32 - A->bits);
+    if (A->rows > 0 && !A->strip_ptr) return fail(CMRS_ERR_INVALID_VALUE, "strip_ptr is NULL");
+    if (A->nnz > 0 && (!A->col_word || !A->val)) return fail(CMRS_ERR_INVALID_VALUE, "col_word or val is NULL");
+    return CMRS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t cmrs_abi_version(void) { return CMRS_ABI_VERSION; }
+
+int32_t cmrs_num_strips(int32_t rows, int32_t height) {
+    if (rows < 0 || height < 1) return -1;
+    return static_cast<int32_t>((static_cast<int64_t>(rows) + height - 1) / height);
+}
+
+int32_t cmrs_bits_for_height(int32_t height) {
+    if (height < 1 || height > CMRS_MAX_HEIGHT) return -1;
+    int32_t b = 0;
+    while ((1 << b) < height) ++b;
+    return b < 4 ? 4 : b;
+}
+
+size_t cmrs_from_csr_workspace(int32_t rows, int32_t nnz, int32_t height, uint32_t flags) {
+    (void)rows;
+    (void)height;
+    if (!(flags & CMRS_SORT) || nnz <= 0) return 0;
+    return cmrs::from_csr_workspace_layout(nnz).total;
+}
+
+cmrs_status_t cmrs_from_csr(int32_t rows, int32_t cols, int32_t nnz, const int32_t* row_ptr, const int32_t* col_ind,
+                            const void* val_in, cmrs_dtype_t dtype, int32_t height, uint32_t flags,
+                            int32_t* strip_ptr_out, uint32_t* col_word_out, void* val_out, void* workspace,
+                            size_t workspace_bytes, hipStream_t stream) {
+    g_last_error[0] = 0;
+    if (rows < 0 || cols < 0 || nnz < 0)
+        return fail(CMRS_ERR_INVALID_VALUE, "negative size (rows=%d cols=%d nnz=%d)", rows, cols, nnz);
+    if (height < 1 || height > CMRS_MAX_HEIGHT)
+        return fail(CMRS_ERR_INVALID_VALUE, "height %d outside [1, %d]", height, CMRS_MAX_HEIGHT);
+    if (flags & ~CMRS_SORT) return fail(CMRS_ERR_INVALID_VALUE, "unknown flags 0x%x", flags);
+    if (!valid_dtype(dtype)) return fail(CMRS_ERR_INVALID_VALUE, "unknown dtype %d", (int)dtype);
+    const int32_t bits = cmrs_bits_for_height(height);
+    if (!cols_fit(cols, bits))
+        return fail(CMRS_ERR_INDEX_OVERFLOW, "cols=%d does not fit %d column bits", cols, 32 - bits);
+    if (!row_ptr || !strip_ptr_out) return fail(CMRS_ERR_INVALID_VALUE, "row_ptr or strip_ptr_out is NULL");
+    if (nnz > 0 && (!col_ind || !val_in || !col_word_out || !val_out))
+        return fail(CMRS_ERR_INVALID_VALUE, "an nnz-sized array is NULL");
+    const size_t es = cmrs::dtype_bytes(dtype);
+    const size_t nz = static_cast<size_t>(nnz);
+    if (flags & CMRS_SORT) {
+        if (ranges_overlap(col_word_out, 4 * nz, col_ind, 4 * nz) || ranges_overlap(val_out, es * nz, val_in, es * nz) ||
+            ranges_overlap(col_word_out, 4 * nz, val_in, es * nz) || ranges_overlap(val_out, es * nz, col_ind, 4 * nz))
+            return fail(CMRS_ERR_INVALID_VALUE, "sorted conversion cannot run in place");
+        const size_t need = cmrs_from_csr_workspace(rows, nnz, height, flags);
+        if (need > 0 && (!workspace || workspace_bytes < need))
+            return fail(CMRS_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace_bytes);
+    } else {
+        // In place is allowed only as exact aliasing.
+        if ((ranges_overlap(col_word_out, 4 * nz, col_ind, 4 * nz) && (const void*)col_word_out != (const void*)col_ind) ||
+            (ranges_overlap(val_out, es * nz, val_in, es * nz) && val_out != val_in))
+            return fail(CMRS_ERR_INVALID_VALUE, "outputs partially overlap inputs");
+    }
+    return from_hip(cmrs::launch_from_csr(rows, cols, nnz, row_ptr, col_ind, val_in, dtype, height, bits, flags,
+                                          strip_ptr_out, col_word_out, val_out, workspace, stream),
+                    "cmrs_from_csr");
+}
+
+size_t cmrs_to_csr_workspace(const cmrs_mat_t* A) {
+    (void)A;
+    return 0;
+}
+
+cmrs_status_t cmrs_to_csr(const cmrs_mat_t* A, int32_t* row_ptr_out, int32_t* col_ind_out, void* val_out,
+                          void* workspace, size_t workspace_bytes, hipStream_t stream) {
+    (void)workspace;
+    (void)workspace_bytes;
+    g_last_error[0] = 0;
+    cmrs_status_t st = check_mat(A);
+    if (st != CMRS_OK) return st;
+    if (!row_ptr_out) return fail(CMRS_ERR_INVALID_VALUE, "row_ptr_out is NULL");
+    if (A->nnz > 0 && (!col_ind_out || !val_out)) return fail(CMRS_ERR_INVALID_VALUE, "col_ind_out or val_out is NULL");
+    const size_t es = cmrs::dtype_bytes(A->val_dtype);
+    const size_t nz = static_cast<size_t>(A->nnz);
+    if (ranges_overlap(col_ind_out, 4 * nz, A->col_word, 4 * nz) || ranges_overlap(val_out, es * nz, A->val, es * nz))
+        return fail(CMRS_ERR_INVALID_VALUE, "outputs overlap inputs");
+    return from_hip(cmrs::launch_to_csr(A, row_ptr_out, col_ind_out, val_out, stream), "cmrs_to_csr");
+}
+
+cmrs_status_t cmrs_spmv(const cmrs_mat_t* A, const void* x, void* y, cmrs_dtype_t xy_dtype, int32_t variant,
+                        hipStream_t stream) {
+    g_last_error[0] = 0;
+    cmrs_status_t st = check_mat(A);
+    if (st != CMRS_OK) return st;
+    const bool ok_types = (A->val_dtype == CMRS_R64F && xy_dtype == CMRS_R64F) ||
+                          (A->val_dtype == CMRS_R32F && xy_dtype == CMRS_R32F) ||
+                          (A->val_dtype == CMRS_R16BF && xy_dtype == CMRS_R32F);
+    if (!ok_types)
+        return fail(CMRS_ERR_NOT_SUPPORTED, "value dtype %d with x/y dtype %d", (int)A->val_dtype, (int)xy_dtype);
+    if (variant < CMRS_SPMV_AUTO || variant > CMRS_SPMV_REG)
+        return fail(CMRS_ERR_INVALID_VALUE, "unknown variant %d", variant);
+    if (A->rows == 0) return CMRS_OK;
+    if (!y || (A->cols > 0 && !x)) return fail(CMRS_ERR_INVALID_VALUE, "x or y is NULL");
+    const size_t xs = cmrs::dtype_bytes(xy_dtype);
+    if (ranges_overlap(x, xs * static_cast<size_t>(A->cols), y, xs * static_cast<size_t>(A->rows)))
+        return fail(CMRS_ERR_INVALID_VALUE, "x and y overlap");
+    return from_hip(cmrs::launch_spmv(A, x, y, xy_dtype, variant, stream), "cmrs_spmv");
+}
+
+cmrs_status_t cmrs_validate_csr(int32_t rows, int32_t cols, int32_t nnz, const int32_t* row_ptr,
+                                const int32_t* col_ind, int32_t* flag_out, hipStream_t stream) {
+    g_last_error[0] = 0;
+    if (rows < 0 || cols < 0 || nnz < 0) return fail(CMRS_ERR_INVALID_VALUE, "negative size");
+    if (!row_ptr || !flag_out || (nnz > 0 && !col_ind)) return fail(CMRS_ERR_INVALID_VALUE, "NULL pointer");
+    return from_hip(cmrs::launch_validate_csr(rows, cols, nnz, row_ptr, col_ind, flag_out, stream),
+                    "cmrs_validate_csr");
+}
+
+const char* cmrs_status_string(cmrs_status_t s) {
+    switch (s) {
+        case CMRS_OK: return "CMRS_OK";
+        case CMRS_ERR_INVALID_VALUE: return "CMRS_ERR_INVALID_VALUE";
+        case CMRS_ERR_INDEX_OVERFLOW: return "CMRS_ERR_INDEX_OVERFLOW";
+        case CMRS_ERR_NOT_SUPPORTED: return "CMRS_ERR_NOT_SUPPORTED";
+        case CMRS_ERR_DEVICE: return "CMRS_ERR_DEVICE";
+        case CMRS_ERR_WORKSPACE: return "CMRS_ERR_WORKSPACE";
+    }
+    return "CMRS_UNKNOWN_STATUS";
+}
+
+const char* cmrs_last_error(void) { return g_last_error; }
+
+}  // extern "C"

@@ -1,0 +1,56 @@
+// Host-side declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "cmrs.h"
+
+namespace cmrs {
+
+inline int next_pow2(int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+inline size_t dtype_bytes(cmrs_dtype_t t) {
+    switch (t) {
+        case CMRS_R64F: return 8;
+        case CMRS_R32F: return 4;
+        case CMRS_R16BF: return 2;
+    }
+    return 0;
+}
+
+// Strips that one wave sorts in its LDS slice (sorted conversion), and the
+// largest strip a 1024-thread workgroup sorts in LDS; longer strips are
+// sorted in the global workspace.
+constexpr int kWaveSortCap = 1024;
+constexpr int kBlockSortCap = 16384;
+
+struct FromCsrWorkspaceLayout {
+    size_t list_off;    // int32 count at offset 0, list of long strips at list_off
+    size_t list_cap;    // entries of the list
+    size_t global_off;  // uint64 sort area: 2*nnz entries
+    size_t total;
+};
+FromCsrWorkspaceLayout from_csr_workspace_layout(int32_t nnz);
+
+hipError_t launch_from_csr(int32_t rows, int32_t cols, int32_t nnz, const int32_t* row_ptr,
+                           const int32_t* col_ind, const void* val_in, cmrs_dtype_t dtype, int32_t height,
+                           int32_t bits, uint32_t flags, int32_t* strip_ptr, uint32_t* col_word, void* val_out,
+                           void* workspace, hipStream_t stream);
+
+hipError_t launch_to_csr(const cmrs_mat_t* A, int32_t* row_ptr, int32_t* col_ind, void* val_out,
+                         hipStream_t stream);
+
+hipError_t launch_spmv(const cmrs_mat_t* A, const void* x, void* y, cmrs_dtype_t xy_dtype, int variant,
+                       hipStream_t stream);
+int resolve_spmv_variant(const cmrs_mat_t* A, int variant);
+
+hipError_t launch_validate_csr(int32_t rows, int32_t cols, int32_t nnz, const int32_t* row_ptr,
+                               const int32_t* col_ind, int32_t* flag, hipStream_t stream);
+
+}  // namespace cmrs

@@ -1,0 +1,124 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/cmrs.h declares, and its host-side logic (sizes, argument validation)
+behaves as documented.  No call here reaches a kernel launch."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cmrs.h")
+
+
+@pytest.fixture(scope="module")
+def C():
+    from paper_1203_2946_amd import cmrs
+    return cmrs
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cmrs_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("cmrs_from_csr", "cmrs_to_csr", "cmrs_spmv", "cmrs_num_strips", "cmrs_bits_for_height",
+              "cmrs_status_string", "cmrs_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(C):
+    lib = ctypes.CDLL(C.LIB_PATH)
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+    assert sorted(C.EXPORTED) == sorted(declared_functions())
+
+
+def test_abi_version(C):
+    assert C.abi_version() == 1
+
+
+def test_host_helpers(C):
+    assert C.num_strips(5, 2) == 3 and C.num_strips(0, 7) == 0 and C.num_strips(2**31 - 1, 32) == 2**26
+    assert C.num_strips(-1, 2) == -1 and C.num_strips(4, 0) == -1
+    assert [C.bits_for_height(h) for h in (1, 2, 3, 16, 17, 32)] == [4, 4, 4, 4, 5, 5]
+    assert C.bits_for_height(0) == -1 and C.bits_for_height(33) == -1
+    assert C.lib.cmrs_status_string(3).decode() == "CMRS_ERR_NOT_SUPPORTED"
+    assert C.lib.cmrs_status_string(99).decode() == "CMRS_UNKNOWN_STATUS"
+
+
+def test_workspace_sizes(C):
+    assert C.from_csr_workspace_bytes(100, 1000, 8, sort=False) == 0
+    ws = C.from_csr_workspace_bytes(100, 1000, 8, sort=True)
+    assert ws >= 16 * 1000
+    assert C.from_csr_workspace_bytes(100, 0, 8, sort=True) == 0
+
+
+FAKE = 0x1000  # never dereferenced: every call below fails its host checks first
+
+
+def _from_csr(C, **kw):
+    a = dict(rows=4, cols=4, nnz=4, row_ptr=FAKE, col_ind=FAKE, val=FAKE, dtype=0, height=2, flags=0,
+             sp=FAKE, cw=FAKE + 64, vo=FAKE + 128, ws=None, wsb=0)
+    a.update(kw)
+    return C.lib.cmrs_from_csr(a["rows"], a["cols"], a["nnz"], a["row_ptr"], a["col_ind"], a["val"], a["dtype"],
+                               a["height"], a["flags"], a["sp"], a["cw"], a["vo"], a["ws"], a["wsb"], None)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(rows=-1), 1), (dict(nnz=-3), 1), (dict(height=0), 1), (dict(height=33), 1), (dict(flags=2), 1),
+    (dict(dtype=7), 1), (dict(row_ptr=None), 1), (dict(col_ind=None), 1), (dict(sp=None), 1),
+    (dict(cols=2**28 + 1), 2), (dict(cols=2**27 + 1, height=17), 2),
+    (dict(flags=1, ws=None, wsb=0), 5),
+    (dict(flags=1, cw=FAKE + 8, col_ind=FAKE + 8, ws=FAKE, wsb=1 << 20), 1),
+    (dict(cw=FAKE + 4, col_ind=FAKE), 1),
+])
+def test_from_csr_rejects(C, kw, status):
+    assert _from_csr(C, **kw) == status
+    assert C.lib.cmrs_last_error().decode() != ""
+
+
+def _mat(C, **kw):
+    d = dict(rows=4, cols=4, nnz=4, height=2, bits=4, sorted=0, val_dtype=0, strip_ptr=FAKE, col_word=FAKE,
+             val=FAKE)
+    d.update(kw)
+    return C.CmrsMatDesc(**d)
+
+
+@pytest.mark.parametrize("kw,xy,variant,status", [
+    (dict(height=0), 0, 0, 1), (dict(bits=5), 0, 0, 1), (dict(val_dtype=9), 0, 0, 1),
+    (dict(strip_ptr=None), 0, 0, 1), (dict(cols=2**28 + 1), 0, 0, 2),
+    (dict(), 1, 0, 3), (dict(val_dtype=1), 0, 0, 3), (dict(val_dtype=2), 2, 0, 3),
+    (dict(), 0, 9, 1),
+])
+def test_spmv_rejects(C, kw, xy, variant, status):
+    d = _mat(C, **kw)
+    assert C.lib.cmrs_spmv(ctypes.byref(d), FAKE, FAKE + 4096, xy, variant, None) == status
+
+
+def test_spmv_rejects_overlap_and_null(C):
+    d = _mat(C)
+    assert C.lib.cmrs_spmv(ctypes.byref(d), FAKE, FAKE + 8, 0, 0, None) == 1      # x and y overlap
+    assert C.lib.cmrs_spmv(ctypes.byref(d), FAKE, None, 0, 0, None) == 1
+    assert C.lib.cmrs_spmv(None, FAKE, FAKE + 4096, 0, 0, None) == 1
+
+
+def test_spmv_empty_matrix_is_noop(C):
+    d = _mat(C, rows=0, nnz=0, strip_ptr=None, col_word=None, val=None)
+    assert C.lib.cmrs_spmv(ctypes.byref(d), None, None, 0, 0, None) == 0
+
+
+def test_to_csr_rejects(C):
+    d = _mat(C)
+    assert C.lib.cmrs_to_csr(ctypes.byref(d), None, FAKE, FAKE, None, 0, None) == 1
+    assert C.lib.cmrs_to_csr(ctypes.byref(d), FAKE + 4096, FAKE, FAKE + 8192, None, 0, None) == 1  # col_ind_out overlaps col_word
+    d2 = _mat(C, nnz=-1)
+    assert C.lib.cmrs_to_csr(ctypes.byref(d2), FAKE, FAKE, FAKE, None, 0, None) == 1
+
+
+def test_validate_rejects(C):
+    assert C.lib.cmrs_validate_csr(-1, 4, 4, FAKE, FAKE, FAKE, None) == 1
+    assert C.lib.cmrs_validate_csr(4, 4, 4, None, FAKE, FAKE, None) == 1

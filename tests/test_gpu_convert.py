@@ -1,0 +1,214 @@
+"""GPU parity of the conversions (CSR -> CMRS, CMRS -> CSR) against the oracle.
+
+Bar: bit-exact on every array (strip pointers, packed words, value bits),
+through the C ABI, for every height 1..32, sorted and unsorted, on seeded
+inputs that span many strips and a ragged last strip, at full workload sizes,
+and on the edge cases (no rows, no entries, empty rows and strips, strips
+longer than a wave's and a workgroup's sort capacity, rectangular shapes).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_example.json")
+
+
+@pytest.fixture(scope="module")
+def C():
+    from paper_1203_2946_amd import cmrs
+    return cmrs
+
+
+def check_from_csr(C, A, height, sort, dtype="f64", in_place=False):
+    rp, ci, v, hv = G.upload(A, dtype)
+    M = C.from_csr(rp, ci, v, A.cols, height, sort=sort, in_place=in_place)
+    torch.cuda.synchronize()
+    esp, ew, ev = oracle.csr_to_cmrs(A.row_ptr, A.col_ind, hv, A.cols, height, sorted_=sort)
+    assert np.array_equal(M.strip_ptr.cpu().numpy(), esp), "strip_ptr"
+    assert np.array_equal(G.words(M.col_word), ew), "col_word"
+    assert np.array_equal(G.val_bits(M.val), G.np_bits(ev)), "val"
+    return M, hv
+
+
+def check_round_trip(C, A, M, hv):
+    rp2, ci2, v2 = C.to_csr(M)
+    torch.cuda.synchronize()
+    erp, eci, ev = oracle.cmrs_to_csr(M.strip_ptr.cpu().numpy(), G.words(M.col_word), G.val_bits(M.val).view(hv.dtype),
+                                      A.rows, M.height)
+    assert np.array_equal(rp2.cpu().numpy(), erp), "row_ptr vs oracle"
+    assert np.array_equal(ci2.cpu().numpy(), eci), "col_ind vs oracle"
+    assert np.array_equal(G.val_bits(v2), G.np_bits(ev)), "val vs oracle"
+    return rp2, ci2, v2
+
+
+def test_paper_example(C):
+    P = json.load(open(GOLDEN))
+    c = P["crs"]
+    A = synth.Csr(5, 5, np.array(c["RowPtr"], np.int32), np.array(c["ColInd"], np.int32),
+                  np.array(c["Val"], np.float64))
+    for key, sort in (("cmrs_h2", False), ("cmrs_h2_sorted", True)):
+        M, _ = check_from_csr(C, A, 2, sort)
+        exp = P[key]
+        w = G.words(M.col_word)
+        assert M.strip_ptr.cpu().tolist() == exp["StripPtr"]
+        assert (w >> 4).tolist() == exp["ColInd"]
+        assert (w & 15).tolist() == exp["RowInStrip"]
+        assert M.val.cpu().tolist() == [float(a) for a in exp["Val"]]
+
+
+@pytest.mark.parametrize("height", list(range(1, 33)))
+@pytest.mark.parametrize("sort", [False, True])
+def test_random_all_heights(C, height, sort):
+    A = synth.random_csr(517, 300, max_row=20, seed=height, canonical=sort or height % 2 == 0,
+                         duplicates=(not sort) and height % 3 == 0, explicit_zeros=True)
+    M, hv = check_from_csr(C, A, height, sort)
+    rp2, ci2, v2 = check_round_trip(C, A, M, hv)
+    # round trip returns the input itself (sorted: the input is canonical)
+    assert np.array_equal(rp2.cpu().numpy(), A.row_ptr) and np.array_equal(ci2.cpu().numpy(), A.col_ind)
+    assert np.array_equal(G.val_bits(v2), A.val.view(np.uint64))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("sort", [False, True])
+@pytest.mark.parametrize("height", [2, 4, 8])
+def test_laplacian_64(C, dtype, sort, height):
+    A = synth.laplace2d(64)
+    M, hv = check_from_csr(C, A, height, sort, dtype)
+    rp2, ci2, v2 = check_round_trip(C, A, M, hv)
+    assert np.array_equal(rp2.cpu().numpy(), A.row_ptr) and np.array_equal(ci2.cpu().numpy(), A.col_ind)
+    assert np.array_equal(G.val_bits(v2), G.np_bits(hv))
+
+
+@pytest.mark.parametrize("height", [3, 8, 32])
+def test_in_place_unsorted(C, height):
+    A = synth.random_csr(300, 200, max_row=12, seed=11, canonical=False)
+    rp, ci, v, hv = G.upload(A)
+    ci_ptr, v_ptr = ci.data_ptr(), v.data_ptr()
+    M = C.from_csr(rp, ci, v, A.cols, height, in_place=True)
+    assert M.col_word.data_ptr() == ci_ptr and M.val.data_ptr() == v_ptr
+    torch.cuda.synchronize()
+    esp, ew, ev = oracle.csr_to_cmrs(A.row_ptr, A.col_ind, hv, A.cols, height)
+    assert np.array_equal(M.strip_ptr.cpu().numpy(), esp)
+    assert np.array_equal(G.words(M.col_word), ew)
+    assert np.array_equal(G.val_bits(M.val), G.np_bits(ev))
+
+
+def test_edge_empty(C):
+    # no rows
+    A0 = synth.Csr(0, 5, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    for sort in (False, True):
+        M = C.from_csr(*G.upload(A0)[:3], A0.cols, 4, sort=sort)
+        rp2, ci2, v2 = C.to_csr(M)
+        torch.cuda.synchronize()
+        assert M.strip_ptr.cpu().tolist() == [0]
+        assert rp2.cpu().tolist() == [0] and ci2.numel() == 0
+    # rows but no entries
+    A1 = synth.Csr(10, 3, np.zeros(11, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    for sort in (False, True):
+        M, hv = check_from_csr(C, A1, 4, sort)
+        check_round_trip(C, A1, M, hv)
+    # single row, single column
+    A2 = synth.Csr(1, 1, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([2.5]))
+    for h in (1, 2, 32):
+        M, hv = check_from_csr(C, A2, h, True)
+        check_round_trip(C, A2, M, hv)
+
+
+@pytest.mark.parametrize("shape", [(1000, 37), (37, 5000)])
+def test_rectangular(C, shape):
+    A = synth.random_csr(shape[0], shape[1], max_row=30, seed=4)
+    for h in (1, 5, 16):
+        for sort in (False, True):
+            M, hv = check_from_csr(C, A, h, sort)
+            check_round_trip(C, A, M, hv)
+
+
+def _long_strip_matrix(rows, cols, long_rows, long_len, seed):
+    """Mostly short rows plus a few rows of long_len entries (long strips)."""
+    rng = np.random.default_rng(seed)
+    k = rng.integers(0, 4, rows)
+    k[long_rows] = long_len
+    cl = [np.sort(rng.choice(cols, size=int(kk), replace=False)) for kk in k]
+    col = np.concatenate(cl)
+    rp = np.zeros(rows + 1, np.int64)
+    np.cumsum(k, out=rp[1:])
+    return synth.Csr(rows, cols, rp.astype(np.int32), col.astype(np.int32), rng.standard_normal(col.size))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_long_strips_sorted(C, dtype):
+    """Strips beyond the per-wave (1024) and per-workgroup (16384) LDS sort
+    capacities take the workgroup and the global-workspace sort paths."""
+    A = _long_strip_matrix(4000, 60000, [5, 6, 1000, 1001, 1002, 3999], 9000, seed=1)
+    for h in (2, 4, 8):
+        M, hv = check_from_csr(C, A, h, True, dtype)
+        rp2, ci2, v2 = check_round_trip(C, A, M, hv)
+        assert np.array_equal(ci2.cpu().numpy(), A.col_ind)
+
+
+def test_long_strips_unsorted_noncanonical(C):
+    A = _long_strip_matrix(3000, 40000, [7, 8, 9], 20000, seed=2)
+    rng = np.random.default_rng(3)
+    for i in range(A.rows):
+        a, b = A.row_ptr[i], A.row_ptr[i + 1]
+        A.col_ind[a:b] = rng.permutation(A.col_ind[a:b])
+    for h in (4, 16):
+        M, hv = check_from_csr(C, A, h, False)
+        rp2, ci2, v2 = check_round_trip(C, A, M, hv)
+        assert np.array_equal(ci2.cpu().numpy(), A.col_ind)
+        M2, hv2 = check_from_csr(C, A, h, True)   # sorted from non-canonical input: oracle decides
+        check_round_trip(C, A, M2, hv2)
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return synth.poisson_rows(1 << 20, 16.0, seed=0)
+
+
+@pytest.fixture(scope="module")
+def c3():
+    return synth.zipf_clustered(2_000_000, seed=0)
+
+
+@pytest.mark.parametrize("height", [1, 2, 4, 8, 16, 32])
+def test_c2_full_size(C, c2, height):
+    """n = 2^20, Poisson(16) rows: bit-exact conversion both ways, sorted."""
+    M, hv = check_from_csr(C, c2, height, True)
+    rp2, ci2, v2 = C.to_csr(M)
+    torch.cuda.synchronize()
+    assert np.array_equal(rp2.cpu().numpy(), c2.row_ptr) and np.array_equal(ci2.cpu().numpy(), c2.col_ind)
+    assert np.array_equal(G.val_bits(v2), c2.val.view(np.uint64))
+
+
+@pytest.mark.parametrize("height,sort", [(8, True), (8, False), (32, True)])
+def test_c3_full_size(C, c3, height, sort):
+    """n = 2e6, Zipf(2) rows up to 10000 entries: long strips in sorted mode."""
+    M, hv = check_from_csr(C, c3, height, sort)
+    rp2, ci2, v2 = C.to_csr(M)
+    torch.cuda.synchronize()
+    assert np.array_equal(rp2.cpu().numpy(), c3.row_ptr) and np.array_equal(ci2.cpu().numpy(), c3.col_ind)
+    assert np.array_equal(G.val_bits(v2), c3.val.view(np.uint64))
+
+
+def test_validate_csr(C):
+    A = synth.random_csr(100, 50, seed=1)
+    rp, ci, _, _ = G.upload(A)
+    assert C.validate_csr(rp, ci, A.cols) == 0
+    bad = ci.clone()
+    bad[3] = 50
+    assert C.validate_csr(rp, bad, A.cols) & 4
+    rpb = rp.clone()
+    rpb[10] = rpb[11] + 1
+    assert C.validate_csr(rpb, ci, A.cols) & 2
+    rpc = rp.clone()
+    rpc[-1] += 1
+    assert C.validate_csr(rpc, ci, A.cols) & 1
