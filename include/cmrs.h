@@ -66,6 +66,10 @@ typedef enum {
 #define CMRS_SPMV_AUTO 0   /* library's choice for (height, dtype)                  */
 #define CMRS_SPMV_LDS 1    /* one wave64 per strip, per-lane partial sums in LDS     */
 #define CMRS_SPMV_REG 2    /* one wave64 per strip, per-lane partial sums in VGPRs   */
+#define CMRS_SPMV_LDS_NT 3 /* LDS, Val / word streams read with non-temporal loads   */
+#define CMRS_SPMV_REG_NT 4 /* REG, Val / word streams read with non-temporal loads   */
+#define CMRS_SPMV_GROUP 5  /* 64/G strips per wave, G lanes per strip, LDS partials  */
+#define CMRS_SPMV_GROUP_NT 6 /* GROUP with non-temporal Val / word loads             */
 
 /*
  * A CMRS matrix (Sec. 3): `height` rows per strip, strips = ceil(rows/height).
@@ -168,6 +172,32 @@ cmrs_status_t cmrs_to_csr(const cmrs_mat_t *A, int32_t *row_ptr_out, int32_t *co
  */
 cmrs_status_t cmrs_spmv(const cmrs_mat_t *A, const void *x, void *y, cmrs_dtype_t xy_dtype,
                         int32_t variant, hipStream_t stream);
+
+/*
+ * Column-blocked schedule (an MI355X-specific schedule of Algorithm 1, not a
+ * format change).  For a sorted matrix (CMRS_SORT: the entries of every strip
+ * ascend by column) the columns are cut into col_blocks blocks of width
+ * ceil(cols / col_blocks); the entries of a strip that fall in block b are then
+ * one contiguous run.  The plan holds, for every strip s and b = 1 ..
+ * col_blocks-1, the index of the first entry of strip s in block b:
+ *   split[s * (col_blocks - 1) + b - 1]      (int32, device)
+ * cmrs_spmv_colblock then makes col_blocks passes; pass b processes run b of
+ * every strip exactly as cmrs_spmv processes a strip and adds the row sums to
+ * y (pass 0 overwrites y).  Each pass gathers from a 1/col_blocks slice of x,
+ * which stays resident in an XCD's L2 when x is larger than the L2.  Results
+ * obey the same error bound as cmrs_spmv (the products of a row are summed in
+ * a different order) and are deterministic.
+ *   col_blocks   1 .. 64; 1 means no blocking (plan of zero bytes).
+ *   variant      accumulation variant as for cmrs_spmv.
+ * The plan depends only on A's strip_ptr and col_word; rebuild it when they
+ * change.  CMRS_ERR_INVALID_VALUE if A is not sorted.
+ */
+size_t cmrs_colblock_plan_bytes(const cmrs_mat_t *A, int32_t col_blocks);
+cmrs_status_t cmrs_colblock_plan(const cmrs_mat_t *A, int32_t col_blocks, int32_t *split, size_t split_bytes,
+                                 hipStream_t stream);
+cmrs_status_t cmrs_spmv_colblock(const cmrs_mat_t *A, const void *x, void *y, cmrs_dtype_t xy_dtype,
+                                 int32_t variant, int32_t col_blocks, const int32_t *split, size_t split_bytes,
+                                 hipStream_t stream);
 
 /*
  * Device check of CSR validity: writes *flag_out = 0 when row_ptr[0] == 0,

@@ -32,8 +32,9 @@ CMRS_ERR_WORKSPACE = 5
 CMRS_R64F, CMRS_R32F, CMRS_R16BF = 0, 1, 2
 CMRS_SORT = 1
 CMRS_MAX_HEIGHT = 32
-SPMV_AUTO, SPMV_LDS, SPMV_REG = 0, 1, 2
-VARIANTS = {"auto": SPMV_AUTO, "lds": SPMV_LDS, "reg": SPMV_REG}
+SPMV_AUTO, SPMV_LDS, SPMV_REG, SPMV_LDS_NT, SPMV_REG_NT, SPMV_GROUP, SPMV_GROUP_NT = 0, 1, 2, 3, 4, 5, 6
+VARIANTS = {"auto": SPMV_AUTO, "lds": SPMV_LDS, "reg": SPMV_REG, "lds_nt": SPMV_LDS_NT, "reg_nt": SPMV_REG_NT,
+            "group": SPMV_GROUP, "group_nt": SPMV_GROUP_NT}
 
 _DT = {torch.float64: CMRS_R64F, torch.float32: CMRS_R32F, torch.bfloat16: CMRS_R16BF}
 
@@ -60,6 +61,11 @@ lib.cmrs_to_csr.argtypes = [_DP, _vp, _vp, _vp, _vp, _sz, _vp]
 lib.cmrs_to_csr.restype = ctypes.c_int
 lib.cmrs_spmv.argtypes = [_DP, _vp, _vp, ctypes.c_int, _i32, _vp]
 lib.cmrs_spmv.restype = ctypes.c_int
+lib.cmrs_colblock_plan_bytes.argtypes, lib.cmrs_colblock_plan_bytes.restype = [_DP, _i32], _sz
+lib.cmrs_colblock_plan.argtypes = [_DP, _i32, _vp, _sz, _vp]
+lib.cmrs_colblock_plan.restype = ctypes.c_int
+lib.cmrs_spmv_colblock.argtypes = [_DP, _vp, _vp, ctypes.c_int, _i32, _i32, _vp, _sz, _vp]
+lib.cmrs_spmv_colblock.restype = ctypes.c_int
 lib.cmrs_validate_csr.argtypes = [_i32, _i32, _i32, _vp, _vp, _vp, _vp]
 lib.cmrs_validate_csr.restype = ctypes.c_int
 lib.cmrs_status_string.argtypes, lib.cmrs_status_string.restype = [ctypes.c_int], ctypes.c_char_p
@@ -67,6 +73,7 @@ lib.cmrs_last_error.argtypes, lib.cmrs_last_error.restype = [], ctypes.c_char_p
 
 EXPORTED = ["cmrs_abi_version", "cmrs_num_strips", "cmrs_bits_for_height", "cmrs_from_csr_workspace",
             "cmrs_from_csr", "cmrs_to_csr_workspace", "cmrs_to_csr", "cmrs_spmv", "cmrs_validate_csr",
+            "cmrs_colblock_plan_bytes", "cmrs_colblock_plan", "cmrs_spmv_colblock",
             "cmrs_status_string", "cmrs_last_error"]
 
 
@@ -217,6 +224,46 @@ def spmv(A: CmrsMatrix, x: torch.Tensor, out: torch.Tensor | None = None, varian
     d = A.desc()
     st = lib.cmrs_spmv(ctypes.byref(d), _ptr(x), _ptr(y), _DT[xdt], int(variant), _stream(stream))
     _check(st, "cmrs_spmv")
+    return y
+
+
+@dataclass
+class ColblockPlan:
+    """Split points of the column-blocked schedule (int32 [strips, nb-1])."""
+    col_blocks: int
+    split: torch.Tensor | None
+
+    @property
+    def nbytes(self) -> int:
+        return 0 if self.split is None else self.split.numel() * 4
+
+
+def colblock_plan(A: CmrsMatrix, col_blocks: int, stream=None) -> ColblockPlan:
+    d = A.desc()
+    nbytes = int(lib.cmrs_colblock_plan_bytes(ctypes.byref(d), col_blocks))
+    split = torch.empty(max(nbytes // 4, 1), dtype=torch.int32, device=A.col_word.device) if nbytes else None
+    st = lib.cmrs_colblock_plan(ctypes.byref(d), col_blocks, _ptr(split), nbytes, _stream(stream))
+    _check(st, "cmrs_colblock_plan")
+    return ColblockPlan(col_blocks, split)
+
+
+def spmv_colblock(A: CmrsMatrix, plan: ColblockPlan, x: torch.Tensor, out: torch.Tensor | None = None,
+                  variant: int | str = SPMV_AUTO, stream=None) -> torch.Tensor:
+    """y = A x with the column-blocked schedule (A sorted)."""
+    if isinstance(variant, str):
+        variant = VARIANTS[variant]
+    xdt = torch.float64 if A.val.dtype == torch.float64 else torch.float32
+    _dev(x, "x", xdt)
+    if x.numel() != A.cols:
+        raise ValueError(f"x has {x.numel()} entries, the matrix {A.cols} columns")
+    y = out if out is not None else torch.empty(A.rows, dtype=xdt, device=x.device)
+    _dev(y, "y", xdt)
+    if y.numel() != A.rows:
+        raise ValueError("y has the wrong length")
+    d = A.desc()
+    st = lib.cmrs_spmv_colblock(ctypes.byref(d), _ptr(x), _ptr(y), _DT[xdt], int(variant), plan.col_blocks,
+                                _ptr(plan.split), plan.nbytes, _stream(stream))
+    _check(st, "cmrs_spmv_colblock")
     return y
 
 

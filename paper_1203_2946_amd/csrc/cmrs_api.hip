@@ -145,9 +145,8 @@ cmrs_status_t cmrs_to_csr(const cmrs_mat_t* A, int32_t* row_ptr_out, int32_t* co
     return from_hip(cmrs::launch_to_csr(A, row_ptr_out, col_ind_out, val_out, stream), "cmrs_to_csr");
 }
 
-cmrs_status_t cmrs_spmv(const cmrs_mat_t* A, const void* x, void* y, cmrs_dtype_t xy_dtype, int32_t variant,
-                        hipStream_t stream) {
-    g_last_error[0] = 0;
+static cmrs_status_t check_spmv_args(const cmrs_mat_t* A, const void* x, void* y, cmrs_dtype_t xy_dtype,
+                                     int32_t variant) {
     cmrs_status_t st = check_mat(A);
     if (st != CMRS_OK) return st;
     const bool ok_types = (A->val_dtype == CMRS_R64F && xy_dtype == CMRS_R64F) ||
@@ -155,14 +154,64 @@ cmrs_status_t cmrs_spmv(const cmrs_mat_t* A, const void* x, void* y, cmrs_dtype_
                           (A->val_dtype == CMRS_R16BF && xy_dtype == CMRS_R32F);
     if (!ok_types)
         return fail(CMRS_ERR_NOT_SUPPORTED, "value dtype %d with x/y dtype %d", (int)A->val_dtype, (int)xy_dtype);
-    if (variant < CMRS_SPMV_AUTO || variant > CMRS_SPMV_REG)
+    if (variant < CMRS_SPMV_AUTO || variant > CMRS_SPMV_GROUP_NT)
         return fail(CMRS_ERR_INVALID_VALUE, "unknown variant %d", variant);
     if (A->rows == 0) return CMRS_OK;
     if (!y || (A->cols > 0 && !x)) return fail(CMRS_ERR_INVALID_VALUE, "x or y is NULL");
     const size_t xs = cmrs::dtype_bytes(xy_dtype);
     if (ranges_overlap(x, xs * static_cast<size_t>(A->cols), y, xs * static_cast<size_t>(A->rows)))
         return fail(CMRS_ERR_INVALID_VALUE, "x and y overlap");
+    return CMRS_OK;
+}
+
+cmrs_status_t cmrs_spmv(const cmrs_mat_t* A, const void* x, void* y, cmrs_dtype_t xy_dtype, int32_t variant,
+                        hipStream_t stream) {
+    g_last_error[0] = 0;
+    cmrs_status_t st = check_spmv_args(A, x, y, xy_dtype, variant);
+    if (st != CMRS_OK || A->rows == 0) return st;
     return from_hip(cmrs::launch_spmv(A, x, y, xy_dtype, variant, stream), "cmrs_spmv");
+}
+
+size_t cmrs_colblock_plan_bytes(const cmrs_mat_t* A, int32_t col_blocks) {
+    if (!A || col_blocks <= 1 || A->rows <= 0 || A->height < 1) return 0;
+    const size_t strips = static_cast<size_t>(cmrs_num_strips(A->rows, A->height));
+    return strips * static_cast<size_t>(col_blocks - 1) * sizeof(int32_t);
+}
+
+static cmrs_status_t check_colblock(const cmrs_mat_t* A, int32_t col_blocks, const int32_t* split,
+                                    size_t split_bytes) {
+    if (col_blocks < 1 || col_blocks > 64) return fail(CMRS_ERR_INVALID_VALUE, "col_blocks %d outside [1, 64]", col_blocks);
+    if (col_blocks > 1 && !A->sorted) return fail(CMRS_ERR_INVALID_VALUE, "column blocking needs a sorted matrix");
+    const size_t need = cmrs_colblock_plan_bytes(A, col_blocks);
+    if (need > 0 && (!split || split_bytes < need))
+        return fail(CMRS_ERR_WORKSPACE, "plan of %zu bytes needed, %zu given", need, split_bytes);
+    return CMRS_OK;
+}
+
+static inline int colblock_width(const cmrs_mat_t* A, int32_t col_blocks) {
+    const int64_t w = (static_cast<int64_t>(A->cols) + col_blocks - 1) / col_blocks;
+    return static_cast<int>(w < 1 ? 1 : w);
+}
+
+cmrs_status_t cmrs_colblock_plan(const cmrs_mat_t* A, int32_t col_blocks, int32_t* split, size_t split_bytes,
+                                 hipStream_t stream) {
+    g_last_error[0] = 0;
+    cmrs_status_t st = check_mat(A);
+    if (st != CMRS_OK) return st;
+    st = check_colblock(A, col_blocks, split, split_bytes);
+    if (st != CMRS_OK) return st;
+    return from_hip(cmrs::launch_colblock_plan(A, col_blocks, colblock_width(A, col_blocks), split, stream),
+                    "cmrs_colblock_plan");
+}
+
+cmrs_status_t cmrs_spmv_colblock(const cmrs_mat_t* A, const void* x, void* y, cmrs_dtype_t xy_dtype, int32_t variant,
+                                 int32_t col_blocks, const int32_t* split, size_t split_bytes, hipStream_t stream) {
+    g_last_error[0] = 0;
+    cmrs_status_t st = check_spmv_args(A, x, y, xy_dtype, variant);
+    if (st != CMRS_OK || A->rows == 0) return st;
+    st = check_colblock(A, col_blocks, split, split_bytes);
+    if (st != CMRS_OK) return st;
+    return from_hip(cmrs::launch_spmv_colblock(A, x, y, variant, col_blocks, split, stream), "cmrs_spmv_colblock");
 }
 
 cmrs_status_t cmrs_validate_csr(int32_t rows, int32_t cols, int32_t nnz, const int32_t* row_ptr,

@@ -12,7 +12,17 @@
 //        trip in the shader; each lane owns its slots, so the order of the
 //        additions is fixed and the result deterministic).  Any height.
 //   REG  HB accumulators per lane in VGPRs, updated with predicated adds;
-//        the reduction is a register reduce-scatter butterfly.  Small heights.
+//        the reduction is a register reduce-scatter butterfly.  Heights <= 8.
+// Either can read the Val / word streams with non-temporal loads (NT), which
+// keeps them from displacing x in L2.
+//
+// Column-blocked schedule: for a sorted matrix (entries of a strip ascending
+// by column) the entries of strip s with columns in block b are a contiguous
+// run [split(s, b), split(s, b+1)).  Pass b processes run b of every strip and
+// adds it to y (pass 0 writes y), so one pass gathers from a 1/nb slice of x,
+// small enough to stay resident in one XCD's L2.  The split points are the
+// plan built by colblock_plan_kernel.
+//
 // Workgroups hold 4 waves (4 strips); workgroup ids are renumbered so that each
 // XCD processes one contiguous range of strips.
 #include "cmrs_device.hpp"
@@ -22,6 +32,26 @@ namespace cmrs {
 
 constexpr int kSpmvWaves = 4;
 constexpr int kSpmvThreads = kSpmvWaves * kWave;
+
+template <bool NT, typename T>
+__device__ inline T stream_load(const T* p) {
+    if constexpr (NT) {
+        return __builtin_nontemporal_load(p);
+    } else {
+        return *p;
+    }
+}
+
+template <bool NT>
+__device__ inline bf16_t stream_load(const bf16_t* p) {
+    bf16_t v;
+    if constexpr (NT) {
+        v.bits = __builtin_nontemporal_load(&p->bits);
+    } else {
+        v.bits = p->bits;
+    }
+    return v;
+}
 
 // Sum, for each row r < HB, the 64 per-lane partials b[r*64 + l].  Lanes form
 // HB groups of G = 64/HB; group r sums row r: each lane adds HB consecutive
@@ -41,178 +71,398 @@ __device__ inline AT reduce_rows_lds(const AT* b, int lane) {
     return s;
 }
 
-template <int HB, int U, typename VT, typename XT, typename AT>
-__global__ __launch_bounds__(kSpmvThreads) void spmv_lds_kernel(
-    int rows, int strips, int height, int bits, const int* __restrict__ strip_ptr,
-    const uint32_t* __restrict__ word, const VT* __restrict__ val, const XT* __restrict__ x,
-    XT* __restrict__ y) {
-    __shared__ AT buf[kSpmvWaves][HB * kWave];
-    const int lane = lane_id();
-    const int wave = uniform(static_cast<int>(threadIdx.x) / kWave);
-    const int strip = xcd_logical_block(blockIdx.x, gridDim.x) * kSpmvWaves + wave;
-    if (strip >= strips) return;
-    AT* b = buf[wave];
+template <int HB, typename AT>
+struct LdsAcc {
+    AT* b;
+    __device__ inline void init(int lane) {
 #pragma unroll
-    for (int r = 0; r < HB; ++r) b[r * kWave + lane] = AT(0);
-
-    const int s0 = strip_ptr[strip], s1 = strip_ptr[strip + 1];
-    const uint32_t mask = (1u << bits) - 1u;
-    for (int base = s0; base < s1; base += U * kWave) {
-        uint32_t w[U];
-        VT v[U];
-        XT xv[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int j = base + u * kWave + lane;
-            if (j < s1) {
-                w[u] = word[j];
-                v[u] = val[j];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int j = base + u * kWave + lane;
-            if (j < s1) xv[u] = x[w[u] >> bits];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int j = base + u * kWave + lane;
-            if (j < s1) {
-                const AT p = static_cast<AT>(ValTraits<VT>::widen(v[u])) * static_cast<AT>(xv[u]);
-                const int r = static_cast<int>(w[u] & mask) & (HB - 1);
-                atomicAdd(&b[r * kWave + lane], p);
-            }
-        }
+        for (int r = 0; r < HB; ++r) b[r * kWave + lane] = AT(0);
     }
-    wave_lds_sync();
-    const AT s = reduce_rows_lds<HB>(b, lane);
-    constexpr int G = kWave / HB;
-    const int r = lane / G;
-    const int row = strip * height + r;
-    if ((lane % G) == 0 && r < height && row < rows) y[row] = static_cast<XT>(s);
-}
+    __device__ inline void add(uint32_t r, int lane, AT p) {
+        atomicAdd(&b[(static_cast<int>(r) & (HB - 1)) * kWave + lane], p);
+    }
+    // Row sums; lane l holds the sum of row l / (64 / HB).
+    __device__ inline AT finish(int lane) {
+        wave_lds_sync();
+        return reduce_rows_lds<HB>(b, lane);
+    }
+};
 
-template <int HB, int U, typename VT, typename XT, typename AT>
-__global__ __launch_bounds__(kSpmvThreads) void spmv_reg_kernel(
-    int rows, int strips, int height, int bits, const int* __restrict__ strip_ptr,
-    const uint32_t* __restrict__ word, const VT* __restrict__ val, const XT* __restrict__ x,
-    XT* __restrict__ y) {
-    const int lane = lane_id();
-    const int wave = uniform(static_cast<int>(threadIdx.x) / kWave);
-    const int strip = xcd_logical_block(blockIdx.x, gridDim.x) * kSpmvWaves + wave;
-    if (strip >= strips) return;
+template <int HB, typename AT>
+struct RegAcc {
     AT acc[HB];
+    __device__ inline void init(int) {
 #pragma unroll
-    for (int r = 0; r < HB; ++r) acc[r] = AT(0);
-
-    const int s0 = strip_ptr[strip], s1 = strip_ptr[strip + 1];
-    const uint32_t mask = (1u << bits) - 1u;
-    for (int base = s0; base < s1; base += U * kWave) {
-        uint32_t w[U];
-        VT v[U];
-        XT xv[U];
+        for (int r = 0; r < HB; ++r) acc[r] = AT(0);
+    }
+    __device__ inline void add(uint32_t r, int, AT p) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int j = base + u * kWave + lane;
-            if (j < s1) {
-                w[u] = word[j];
-                v[u] = val[j];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int j = base + u * kWave + lane;
-            if (j < s1) xv[u] = x[w[u] >> bits];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int j = base + u * kWave + lane;
-            if (j < s1) {
-                const AT p = static_cast<AT>(ValTraits<VT>::widen(v[u])) * static_cast<AT>(xv[u]);
-                const uint32_t r = w[u] & mask;
-#pragma unroll
-                for (int k = 0; k < HB; ++k) acc[k] += (r == static_cast<uint32_t>(k)) ? p : AT(0);
-            }
-        }
+        for (int k = 0; k < HB; ++k) acc[k] += (r == static_cast<uint32_t>(k)) ? p : AT(0);
     }
     // Reduce-scatter butterfly: at the step with xor offset o, a lane whose
     // bit o is set keeps the upper half of its rows and sends the lower half.
     // After log2(HB) steps lane l holds a partial of row l / (64/HB); the
     // remaining offsets sum the group.
-    int n = HB;
+    __device__ inline AT finish(int lane) {
+        int n = HB;
 #pragma unroll
-    for (int o = kWave / 2; o >= 1; o >>= 1) {
-        if (n > 1) {
-            const bool upper = (lane & o) != 0;
+        for (int o = kWave / 2; o >= 1; o >>= 1) {
+            if (n > 1) {
+                const bool upper = (lane & o) != 0;
 #pragma unroll
-            for (int i = 0; i < HB / 2; ++i) {
-                if (i < n / 2) {
-                    const AT send = upper ? acc[i] : acc[i + n / 2];
-                    const AT keep = upper ? acc[i + n / 2] : acc[i];
-                    acc[i] = keep + __shfl_xor(send, o);
+                for (int i = 0; i < HB / 2; ++i) {
+                    if (i < n / 2) {
+                        const AT send = upper ? acc[i] : acc[i + n / 2];
+                        const AT keep = upper ? acc[i + n / 2] : acc[i];
+                        acc[i] = keep + __shfl_xor(send, o);
+                    }
                 }
+                n >>= 1;
+            } else {
+                acc[0] += __shfl_xor(acc[0], o);
             }
-            n >>= 1;
-        } else {
-            acc[0] += __shfl_xor(acc[0], o);
         }
+        return acc[0];
+    }
+};
+
+// Entries [lo, hi) of one strip into `acc`; U batches of 64 entries have all
+// their stream loads, then all their gathers, in flight together.
+template <int U, bool NT, typename VT, typename XT, typename AT, typename Acc>
+__device__ inline void accumulate_run(Acc& acc, int lo, int hi, int bits, const uint32_t* __restrict__ word,
+                                      const VT* __restrict__ val, const XT* __restrict__ x, int lane) {
+    const uint32_t mask = (1u << bits) - 1u;
+    for (int base = lo; base < hi; base += U * kWave) {
+        uint32_t w[U];
+        VT v[U];
+        XT xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = base + u * kWave + lane;
+            if (j < hi) {
+                w[u] = stream_load<NT>(word + j);
+                v[u] = stream_load<NT>(val + j);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = base + u * kWave + lane;
+            if (j < hi) xv[u] = x[w[u] >> bits];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = base + u * kWave + lane;
+            if (j < hi) {
+                const AT p = static_cast<AT>(ValTraits<VT>::widen(v[u])) * static_cast<AT>(xv[u]);
+                acc.add(w[u] & mask, lane, p);
+            }
+        }
+    }
+}
+
+// One wave per strip.  split == nullptr: the whole strip, y overwritten.
+// Otherwise run `blk` of `nb` column blocks, y overwritten for blk 0 and
+// accumulated for later blocks.
+template <int HB, int U, bool NT, bool REG, typename VT, typename XT, typename AT>
+__global__ __launch_bounds__(kSpmvThreads) void spmv_kernel(
+    int rows, int strips, int height, int bits, const int* __restrict__ strip_ptr,
+    const uint32_t* __restrict__ word, const VT* __restrict__ val, const XT* __restrict__ x, XT* __restrict__ y,
+    const int* __restrict__ split, int nb, int blk) {
+    __shared__ AT buf[REG ? 1 : kSpmvWaves][REG ? 1 : HB * kWave];
+    const int lane = lane_id();
+    const int wave = uniform(static_cast<int>(threadIdx.x) / kWave);
+    const int strip = xcd_logical_block(blockIdx.x, gridDim.x) * kSpmvWaves + wave;
+    if (strip >= strips) return;
+    int lo, hi;
+    if (split == nullptr) {
+        lo = strip_ptr[strip];
+        hi = strip_ptr[strip + 1];
+    } else {
+        const int* sp = split + static_cast<size_t>(strip) * (nb - 1);
+        lo = blk == 0 ? strip_ptr[strip] : sp[blk - 1];
+        hi = blk == nb - 1 ? strip_ptr[strip + 1] : sp[blk];
+    }
+    AT s;
+    if constexpr (REG) {
+        RegAcc<HB, AT> acc;
+        acc.init(lane);
+        accumulate_run<U, NT, VT, XT, AT>(acc, lo, hi, bits, word, val, x, lane);
+        s = acc.finish(lane);
+    } else {
+        LdsAcc<HB, AT> acc{buf[wave]};
+        acc.init(lane);
+        accumulate_run<U, NT, VT, XT, AT>(acc, lo, hi, bits, word, val, x, lane);
+        s = acc.finish(lane);
     }
     constexpr int G = kWave / HB;
     const int r = lane / G;
     const int row = strip * height + r;
-    if ((lane % G) == 0 && r < height && row < rows) y[row] = static_cast<XT>(acc[0]);
+    if ((lane % G) == 0 && r < height && row < rows) {
+        if (split != nullptr && blk > 0)
+            y[row] = static_cast<XT>(static_cast<AT>(y[row]) + s);
+        else
+            y[row] = static_cast<XT>(s);
+    }
+}
+
+// Strip groups: one wave processes NG = 64/G strips at once, G lanes per
+// strip.  Lane q of group g walks entries lo+q, lo+q+G, ... of its strip with
+// U stream loads and then U gathers in flight, so a wave keeps 64*U entries
+// of memory traffic outstanding instead of one strip's.  Partials live in
+// LDS slot (g*HB + r)*G + q (each lane owns its slots, as in Algorithm 1).
+// Strips longer than long_len are skipped by their group and processed
+// afterwards by the whole wave, one at a time, with the per-lane layout of
+// spmv_kernel.  Requires G >= HB.
+template <int HB, int G, int U, bool NT, typename VT, typename XT, typename AT>
+__global__ __launch_bounds__(kSpmvThreads) void spmv_group_kernel(
+    int rows, int strips, int height, int bits, const int* __restrict__ strip_ptr,
+    const uint32_t* __restrict__ word, const VT* __restrict__ val, const XT* __restrict__ x, XT* __restrict__ y,
+    int long_len) {
+    static_assert(G >= HB && G <= kWave, "group width");
+    constexpr int NG = kWave / G;
+    __shared__ AT buf[kSpmvWaves][HB * kWave];
+    const int lane = lane_id();
+    const int wave = uniform(static_cast<int>(threadIdx.x) / kWave);
+    const int strip0 = (xcd_logical_block(blockIdx.x, gridDim.x) * kSpmvWaves + wave) * NG;
+    if (strip0 >= strips) return;
+    const int g = lane / G, q = lane % G;
+    const int strip = strip0 + g;
+    int lo = 0, hi = 0;
+    if (strip < strips) {
+        lo = strip_ptr[strip];
+        hi = strip_ptr[strip + 1];
+    }
+    const bool is_long = hi - lo > long_len;
+    AT* b = buf[wave];
+    const uint32_t mask = (1u << bits) - 1u;
+#pragma unroll
+    for (int r = 0; r < HB; ++r) b[(g * HB + r) * G + q] = AT(0);
+    if (!is_long) {
+        for (int j0 = lo + q; j0 < hi; j0 += U * G) {
+            uint32_t w[U];
+            VT v[U];
+            XT xv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = j0 + u * G;
+                if (j < hi) {
+                    w[u] = stream_load<NT>(word + j);
+                    v[u] = stream_load<NT>(val + j);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = j0 + u * G;
+                if (j < hi) xv[u] = x[w[u] >> bits];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = j0 + u * G;
+                if (j < hi) {
+                    const AT p = static_cast<AT>(ValTraits<VT>::widen(v[u])) * static_cast<AT>(xv[u]);
+                    const int r = static_cast<int>(w[u] & mask) & (HB - 1);
+                    atomicAdd(&b[(g * HB + r) * G + q], p);
+                }
+            }
+        }
+    }
+    wave_lds_sync();
+    {
+        // NG*HB sums of G partials; L = G/HB lanes per sum, HB partials each.
+        constexpr int L = G / HB;
+        const int si = lane / L, part = lane % L;
+        const AT* pp = b + si * G + part * HB;
+        AT s = pp[0];
+#pragma unroll
+        for (int i = 1; i < HB; ++i) s += pp[i];
+#pragma unroll
+        for (int off = L / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+        const int gg = si / HB, rr = si % HB;
+        const bool grp_long = __shfl(static_cast<int>(is_long), gg * G) != 0;
+        const int st = strip0 + gg;
+        const int row = st * height + rr;
+        if (part == 0 && st < strips && !grp_long && rr < height && row < rows) y[row] = static_cast<XT>(s);
+    }
+    uint64_t longs = ballot(is_long && q == 0);
+    if (longs == 0) return;
+    wave_lds_sync();
+    while (longs) {
+        const int leader = __ffsll(static_cast<unsigned long long>(longs)) - 1;
+        longs &= longs - 1;
+        const int llo = __shfl(lo, leader), lhi = __shfl(hi, leader);
+        const int st = strip0 + leader / G;
+        LdsAcc<HB, AT> acc{b};
+        acc.init(lane);
+        accumulate_run<U, NT, VT, XT, AT>(acc, llo, lhi, bits, word, val, x, lane);
+        const AT s = acc.finish(lane);
+        constexpr int GW = kWave / HB;
+        const int r = lane / GW;
+        const int row = st * height + r;
+        if ((lane % GW) == 0 && r < height && row < rows) y[row] = static_cast<XT>(s);
+        wave_lds_sync();
+    }
+}
+
+// Plan of the column-blocked schedule: split[s*(nb-1) + b-1] = first entry of
+// strip s whose column is >= b*bw, for b = 1..nb-1 (strip entries ascending by
+// column).  One wave per strip; the count of entries below each boundary is
+// accumulated with ballots (lane b-1 keeps boundary b).
+__global__ __launch_bounds__(256) void colblock_plan_kernel(int strips, int bits, int bw, int nb,
+                                                            const int* __restrict__ strip_ptr,
+                                                            const uint32_t* __restrict__ word,
+                                                            int* __restrict__ split) {
+    const int lane = lane_id();
+    const int wave = uniform(static_cast<int>(threadIdx.x) / kWave);
+    const int strip = xcd_logical_block(blockIdx.x, gridDim.x) * 4 + wave;
+    if (strip >= strips) return;
+    const int s0 = strip_ptr[strip], s1 = strip_ptr[strip + 1];
+    int below = 0;
+    for (int base = s0; base < s1; base += kWave) {
+        const int e = base + lane;
+        const int c = e < s1 ? static_cast<int>(word[e] >> bits) : 0x7fffffff;
+        const int blk = c / bw;
+        for (int b = 1; b < nb; ++b) {
+            const uint64_t m = ballot(e < s1 && blk < b);
+            if (lane == b - 1) below += __popcll(m);
+        }
+    }
+    if (lane < nb - 1) split[static_cast<size_t>(strip) * (nb - 1) + lane] = s0 + below;
 }
 
 namespace {
 
-template <typename VT, typename XT, typename AT, int HB>
-hipError_t launch_hb(int variant, const cmrs_mat_t* A, int strips, const void* x, void* y,
-                     hipStream_t stream) {
-    const int blocks = (strips + kSpmvWaves - 1) / kSpmvWaves;
+struct Launch {
+    const cmrs_mat_t* A;
+    int strips;
+    const void* x;
+    void* y;
+    const int* split;
+    int nb;
+    hipStream_t stream;
+};
+
+template <typename VT, typename XT, typename AT, int HB, bool NT, bool REG>
+hipError_t launch_one(const Launch& L) {
+    const int blocks = (L.strips + kSpmvWaves - 1) / kSpmvWaves;
     constexpr int U = HB >= 16 ? 4 : 2;
-    const auto* sp = A->strip_ptr;
-    const auto* w = A->col_word;
-    const auto* v = static_cast<const VT*>(A->val);
-    const auto* xx = static_cast<const XT*>(x);
-    auto* yy = static_cast<XT*>(y);
-    if (variant == CMRS_SPMV_REG && HB <= 8) {
-        hipLaunchKernelGGL((spmv_reg_kernel<HB, U, VT, XT, AT>), dim3(blocks), dim3(kSpmvThreads), 0, stream,
-                           A->rows, strips, A->height, A->bits, sp, w, v, xx, yy);
-    } else {
-        hipLaunchKernelGGL((spmv_lds_kernel<HB, U, VT, XT, AT>), dim3(blocks), dim3(kSpmvThreads), 0, stream,
-                           A->rows, strips, A->height, A->bits, sp, w, v, xx, yy);
+    const auto* v = static_cast<const VT*>(L.A->val);
+    const auto* xx = static_cast<const XT*>(L.x);
+    auto* yy = static_cast<XT*>(L.y);
+    const int passes = L.split ? L.nb : 1;
+    for (int b = 0; b < passes; ++b) {
+        hipLaunchKernelGGL((spmv_kernel<HB, U, NT, REG, VT, XT, AT>), dim3(blocks), dim3(kSpmvThreads), 0, L.stream,
+                           L.A->rows, L.strips, L.A->height, L.A->bits, L.A->strip_ptr, L.A->col_word, v, xx, yy,
+                           L.split, L.nb, b);
     }
     return hipGetLastError();
 }
 
-template <typename VT, typename XT, typename AT>
-hipError_t launch_typed(int variant, const cmrs_mat_t* A, int strips, const void* x, void* y,
-                        hipStream_t stream) {
-    switch (next_pow2(A->height)) {
-        case 1: return launch_hb<VT, XT, AT, 1>(variant, A, strips, x, y, stream);
-        case 2: return launch_hb<VT, XT, AT, 2>(variant, A, strips, x, y, stream);
-        case 4: return launch_hb<VT, XT, AT, 4>(variant, A, strips, x, y, stream);
-        case 8: return launch_hb<VT, XT, AT, 8>(variant, A, strips, x, y, stream);
-        case 16: return launch_hb<VT, XT, AT, 16>(variant, A, strips, x, y, stream);
-        default: return launch_hb<VT, XT, AT, 32>(variant, A, strips, x, y, stream);
+template <typename VT, typename XT, typename AT, int HB, int G, bool NT>
+hipError_t launch_group_g(const Launch& L) {
+    constexpr int NG = kWave / G;
+    constexpr int U = 8;
+    const int waves = (L.strips + NG - 1) / NG;
+    const int blocks = (waves + kSpmvWaves - 1) / kSpmvWaves;
+    hipLaunchKernelGGL((spmv_group_kernel<HB, G, U, NT, VT, XT, AT>), dim3(blocks), dim3(kSpmvThreads), 0, L.stream,
+                       L.A->rows, L.strips, L.A->height, L.A->bits, L.A->strip_ptr, L.A->col_word,
+                       static_cast<const VT*>(L.A->val), static_cast<const XT*>(L.x), static_cast<XT*>(L.y),
+                       4 * U * G);
+    return hipGetLastError();
+}
+
+// Group width: about 8 entries per lane for the average strip, at least HB.
+inline int group_width(const cmrs_mat_t* A, int strips, int hb) {
+    const double avg = strips > 0 ? static_cast<double>(A->nnz) / strips : 0.0;
+    int g = 2;
+    while (g < 64 && g * 8 * 1.5 < avg) g <<= 1;
+    return g < hb ? hb : g;
+}
+
+template <typename VT, typename XT, typename AT, int HB, bool NT>
+hipError_t launch_group(const Launch& L) {
+    const int g = group_width(L.A, L.strips, HB);
+    if constexpr (HB <= 2) {
+        if (g <= 2) return launch_group_g<VT, XT, AT, HB, 2, NT>(L);
     }
+    if constexpr (HB <= 4) {
+        if (g <= 4) return launch_group_g<VT, XT, AT, HB, 4, NT>(L);
+    }
+    if constexpr (HB <= 8) {
+        if (g <= 8) return launch_group_g<VT, XT, AT, HB, 8, NT>(L);
+    }
+    if constexpr (HB <= 16) {
+        if (g <= 16) return launch_group_g<VT, XT, AT, HB, 16, NT>(L);
+    }
+    if (g <= 32) return launch_group_g<VT, XT, AT, HB, 32, NT>(L);
+    return launch_group_g<VT, XT, AT, HB, 64, NT>(L);
+}
+
+template <typename VT, typename XT, typename AT, int HB>
+hipError_t launch_hb(int variant, const Launch& L) {
+    if (variant == CMRS_SPMV_GROUP || variant == CMRS_SPMV_GROUP_NT) {
+        if (L.split == nullptr)
+            return variant == CMRS_SPMV_GROUP_NT ? launch_group<VT, XT, AT, HB, true>(L)
+                                                 : launch_group<VT, XT, AT, HB, false>(L);
+        variant = variant == CMRS_SPMV_GROUP_NT ? CMRS_SPMV_LDS_NT : CMRS_SPMV_LDS;
+    }
+    const bool nt = variant == CMRS_SPMV_LDS_NT || variant == CMRS_SPMV_REG_NT;
+    const bool reg = (variant == CMRS_SPMV_REG || variant == CMRS_SPMV_REG_NT) && HB <= 8;
+    if constexpr (HB <= 8) {
+        if (reg) return nt ? launch_one<VT, XT, AT, HB, true, true>(L) : launch_one<VT, XT, AT, HB, false, true>(L);
+    }
+    return nt ? launch_one<VT, XT, AT, HB, true, false>(L) : launch_one<VT, XT, AT, HB, false, false>(L);
+}
+
+template <typename VT, typename XT, typename AT>
+hipError_t launch_typed(int variant, const Launch& L) {
+    switch (next_pow2(L.A->height)) {
+        case 1: return launch_hb<VT, XT, AT, 1>(variant, L);
+        case 2: return launch_hb<VT, XT, AT, 2>(variant, L);
+        case 4: return launch_hb<VT, XT, AT, 4>(variant, L);
+        case 8: return launch_hb<VT, XT, AT, 8>(variant, L);
+        case 16: return launch_hb<VT, XT, AT, 16>(variant, L);
+        default: return launch_hb<VT, XT, AT, 32>(variant, L);
+    }
+}
+
+hipError_t dispatch(int variant, const Launch& L) {
+    if (L.A->val_dtype == CMRS_R64F) return launch_typed<double, double, double>(variant, L);
+    if (L.A->val_dtype == CMRS_R32F) return launch_typed<float, float, float>(variant, L);
+    return launch_typed<bf16_t, float, float>(variant, L);
 }
 
 }  // namespace
 
 int resolve_spmv_variant(const cmrs_mat_t* A, int variant) {
+    (void)A;
     if (variant != CMRS_SPMV_AUTO) return variant;
     return CMRS_SPMV_LDS;
 }
 
 hipError_t launch_spmv(const cmrs_mat_t* A, const void* x, void* y, cmrs_dtype_t xy_dtype, int variant,
                        hipStream_t stream) {
+    (void)xy_dtype;
+    const int strips = (A->rows + A->height - 1) / A->height;
+    if (strips == 0) return hipSuccess;
+    return dispatch(resolve_spmv_variant(A, variant), Launch{A, strips, x, y, nullptr, 1, stream});
+}
+
+hipError_t launch_colblock_plan(const cmrs_mat_t* A, int nb, int bw, int* split, hipStream_t stream) {
+    const int strips = (A->rows + A->height - 1) / A->height;
+    if (strips == 0 || nb <= 1) return hipSuccess;
+    const int blocks = (strips + 3) / 4;
+    hipLaunchKernelGGL(colblock_plan_kernel, dim3(blocks), dim3(256), 0, stream, strips, A->bits, bw, nb,
+                       A->strip_ptr, A->col_word, split);
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv_colblock(const cmrs_mat_t* A, const void* x, void* y, int variant, int nb,
+                                const int* split, hipStream_t stream) {
     const int strips = (A->rows + A->height - 1) / A->height;
     if (strips == 0) return hipSuccess;
     variant = resolve_spmv_variant(A, variant);
-    if (A->val_dtype == CMRS_R64F) return launch_typed<double, double, double>(variant, A, strips, x, y, stream);
-    if (A->val_dtype == CMRS_R32F) return launch_typed<float, float, float>(variant, A, strips, x, y, stream);
-    return launch_typed<bf16_t, float, float>(variant, A, strips, x, y, stream);
+    if (nb <= 1) return dispatch(variant, Launch{A, strips, x, y, nullptr, 1, stream});
+    return dispatch(variant, Launch{A, strips, x, y, split, nb, stream});
 }
 
 }  // namespace cmrs

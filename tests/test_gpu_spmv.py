@@ -66,8 +66,11 @@ def assert_low_bound(A, hv, dtype, xs64, x64, y):
 HEIGHTS = [1, 2, 3, 4, 5, 7, 8, 12, 16, 17, 31, 32]
 
 
+VARIANTS = ["lds", "reg", "lds_nt", "reg_nt", "group", "group_nt"]
+
+
 @pytest.mark.parametrize("height", HEIGHTS)
-@pytest.mark.parametrize("variant", ["lds", "reg"])
+@pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("sort", [False, True])
 def test_integer_exact(C, height, variant, sort):
     A = synth.random_csr(1200, 700, max_row=40, seed=height, int_values=True, canonical=False, duplicates=not sort)
@@ -77,7 +80,7 @@ def test_integer_exact(C, height, variant, sort):
 
 
 @pytest.mark.parametrize("height", HEIGHTS)
-@pytest.mark.parametrize("variant", ["lds", "reg"])
+@pytest.mark.parametrize("variant", VARIANTS)
 def test_random_fp64_bound(C, height, variant):
     A = synth.random_csr(2000, 1500, max_row=60, seed=100 + height, explicit_zeros=True)
     x = synth.normal_vector(A.cols, seed=height)
@@ -87,7 +90,7 @@ def test_random_fp64_bound(C, height, variant):
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 @pytest.mark.parametrize("height", [1, 2, 4, 8, 16, 32, 6])
-@pytest.mark.parametrize("variant", ["lds", "reg"])
+@pytest.mark.parametrize("variant", ["lds", "reg", "group_nt"])
 def test_random_low_precision(C, dtype, height, variant):
     A = synth.random_csr(1500, 1100, max_row=50, seed=200 + height)
     x = synth.normal_vector(A.cols, seed=3)
@@ -170,7 +173,7 @@ def test_deterministic(C):
     A = synth.zipf_clustered(200000, seed=3)
     x = synth.uniform_vector(A.cols, seed=4)
     rp, ci, v, _ = G.upload(A)
-    for h, variant in ((8, "lds"), (4, "reg"), (32, "lds")):
+    for h, variant in ((8, "lds"), (4, "reg"), (32, "lds"), (8, "group_nt"), (1, "group")):
         M = C.from_csr(rp, ci, v, A.cols, h, sort=True)
         xt = torch.from_numpy(x).cuda()
         ref = C.spmv(M, xt, variant=variant).clone()
@@ -192,7 +195,7 @@ def test_long_rows(C):
                   rng.standard_normal(int(k.sum())))
     x = synth.normal_vector(cols, seed=6)
     for h in (1, 2, 8, 32):
-        for variant in ("lds", "reg"):
+        for variant in ("lds", "reg", "group", "group_nt"):
             y, _, _ = run(C, A, x, h, sort=True, variant=variant)
             assert_fp64_bound(A, x, y)
 
@@ -209,7 +212,7 @@ def c2x(c2):
 
 @pytest.mark.parametrize("height", [1, 2, 4, 8, 16, 32])
 def test_c2_full_fp64(C, c2, c2x, height):
-    for variant in ("auto", "lds", "reg"):
+    for variant in ("auto", "lds", "reg", "group_nt"):
         y, _, _ = run(C, c2, c2x, height, sort=True, variant=variant)
         assert_fp64_bound(c2, c2x, y)
 
@@ -228,9 +231,57 @@ def c3():
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 def test_c3_full(C, c3, dtype):
     x = synth.uniform_vector(c3.cols, seed=1)
-    for h in (4, 8):
-        y, hv, xs = run(C, c3, x, h, dtype, sort=True)
+    for h, variant in ((4, "auto"), (8, "auto"), (8, "group_nt"), (8, "lds")):
+        y, hv, xs = run(C, c3, x, h, dtype, sort=True, variant=variant)
         if dtype == "f64":
             assert_fp64_bound(c3, x, y)
         else:
             assert_low_bound(c3, hv, dtype, xs, x, y)
+
+
+def run_colblock(C, A, x64, height, nb, dtype="f64", variant="auto"):
+    rp, ci, v, hv = G.upload(A, dtype)
+    M = C.from_csr(rp, ci, v, A.cols, height, sort=True)
+    plan = C.colblock_plan(M, nb)
+    xt, xs64 = G.xy_vector(x64, dtype)
+    y = C.spmv_colblock(M, plan, xt, variant=variant)
+    torch.cuda.synchronize()
+    return y.cpu().numpy().astype(np.float64), hv, xs64, M, plan
+
+
+@pytest.mark.parametrize("nb", [1, 2, 3, 7, 16, 64])
+@pytest.mark.parametrize("height", [1, 4, 8, 32])
+def test_colblock(C, nb, height):
+    A = synth.random_csr(3000, 2000, max_row=40, seed=nb + height, int_values=True)
+    x = np.random.default_rng(nb).integers(-7, 8, A.cols).astype(np.float64)
+    for variant in ("lds", "reg", "group_nt"):
+        y, _, _, M, plan = run_colblock(C, A, x, height, nb, variant=variant)
+        assert np.array_equal(y, oracle.csr_spmv(A.row_ptr, A.col_ind, A.val, x))
+    if nb > 1:
+        # plan: first entry of each strip at or beyond each block boundary
+        sp = M.strip_ptr.cpu().numpy()
+        col = G.words(M.col_word) >> M.bits
+        split = plan.split.cpu().numpy()[: M.strips * (nb - 1)].reshape(M.strips, nb - 1)
+        bw = -(-A.cols // nb)
+        for s in range(0, M.strips, max(1, M.strips // 50)):
+            c = col[sp[s]:sp[s + 1]]
+            for b in range(1, nb):
+                assert split[s, b - 1] == sp[s] + int(np.sum(c < b * bw))
+
+
+def test_colblock_bounds_fp64_fp32(C):
+    A = synth.poisson_rows(300000, 16.0, seed=5)
+    x = synth.normal_vector(A.cols, seed=6)
+    for nb in (2, 4):
+        y, _, _, _, _ = run_colblock(C, A, x, 8, nb)
+        assert_fp64_bound(A, x, y)
+        y, hv, xs, _, _ = run_colblock(C, A, x, 8, nb, "f32")
+        assert_low_bound(A, hv, "f32", xs, x, y)
+
+
+def test_colblock_needs_sorted(C):
+    A = synth.random_csr(100, 100, seed=1)
+    rp, ci, v, _ = G.upload(A)
+    M = C.from_csr(rp, ci, v, A.cols, 4, sort=False)
+    with pytest.raises(C.CmrsError):
+        C.colblock_plan(M, 4)
