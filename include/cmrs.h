@@ -181,23 +181,35 @@ cmrs_status_t cmrs_spmv(const cmrs_mat_t *A, const void *x, void *y, cmrs_dtype_
  * one contiguous run.  The plan holds, for every strip s and b = 1 ..
  * col_blocks-1, the index of the first entry of strip s in block b:
  *   split[s * (col_blocks - 1) + b - 1]      (int32, device)
- * cmrs_spmv_colblock then makes col_blocks passes; pass b processes run b of
- * every strip exactly as cmrs_spmv processes a strip and adds the row sums to
- * y (pass 0 overwrites y).  Each pass gathers from a 1/col_blocks slice of x,
- * which stays resident in an XCD's L2 when x is larger than the L2.  Results
- * obey the same error bound as cmrs_spmv (the products of a row are summed in
- * a different order) and are deterministic.
+ * Every run is processed exactly as cmrs_spmv processes a strip; the gathers
+ * of one run touch only 1/col_blocks of x.  Two schedules:
+ *   CMRS_COLBLOCK_PASSES      col_blocks launches, pass b adds run b of every
+ *                             strip to y (pass 0 overwrites y); no workspace.
+ *   CMRS_COLBLOCK_CONCURRENT  one launch; workgroup w takes column block
+ *                             w % col_blocks, so with col_blocks = 8 each of
+ *                             MI355X's 8 XCDs gathers from one eighth of x,
+ *                             which stays in its L2.  Run sums go to a
+ *                             workspace of col_blocks * rows partials (fp64
+ *                             for fp64 values, fp32 otherwise), then a second
+ *                             kernel adds the col_blocks partials of each row
+ *                             in block order.
+ * Results obey the same error bound as cmrs_spmv (the products of a row are
+ * summed in a different order) and are deterministic.
  *   col_blocks   1 .. 64; 1 means no blocking (plan of zero bytes).
- *   variant      accumulation variant as for cmrs_spmv.
+ *   variant      accumulation variant as for cmrs_spmv (the concurrent
+ *                schedule always uses strip groups with non-temporal loads).
  * The plan depends only on A's strip_ptr and col_word; rebuild it when they
  * change.  CMRS_ERR_INVALID_VALUE if A is not sorted.
  */
+#define CMRS_COLBLOCK_PASSES 0
+#define CMRS_COLBLOCK_CONCURRENT 1
 size_t cmrs_colblock_plan_bytes(const cmrs_mat_t *A, int32_t col_blocks);
 cmrs_status_t cmrs_colblock_plan(const cmrs_mat_t *A, int32_t col_blocks, int32_t *split, size_t split_bytes,
                                  hipStream_t stream);
+size_t cmrs_spmv_colblock_workspace(const cmrs_mat_t *A, int32_t col_blocks, int32_t schedule);
 cmrs_status_t cmrs_spmv_colblock(const cmrs_mat_t *A, const void *x, void *y, cmrs_dtype_t xy_dtype,
                                  int32_t variant, int32_t col_blocks, const int32_t *split, size_t split_bytes,
-                                 hipStream_t stream);
+                                 int32_t schedule, void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /*
  * Device check of CSR validity: writes *flag_out = 0 when row_ptr[0] == 0,

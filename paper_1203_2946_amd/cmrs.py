@@ -64,7 +64,8 @@ lib.cmrs_spmv.restype = ctypes.c_int
 lib.cmrs_colblock_plan_bytes.argtypes, lib.cmrs_colblock_plan_bytes.restype = [_DP, _i32], _sz
 lib.cmrs_colblock_plan.argtypes = [_DP, _i32, _vp, _sz, _vp]
 lib.cmrs_colblock_plan.restype = ctypes.c_int
-lib.cmrs_spmv_colblock.argtypes = [_DP, _vp, _vp, ctypes.c_int, _i32, _i32, _vp, _sz, _vp]
+lib.cmrs_spmv_colblock_workspace.argtypes, lib.cmrs_spmv_colblock_workspace.restype = [_DP, _i32, _i32], _sz
+lib.cmrs_spmv_colblock.argtypes = [_DP, _vp, _vp, ctypes.c_int, _i32, _i32, _vp, _sz, _i32, _vp, _sz, _vp]
 lib.cmrs_spmv_colblock.restype = ctypes.c_int
 lib.cmrs_validate_csr.argtypes = [_i32, _i32, _i32, _vp, _vp, _vp, _vp]
 lib.cmrs_validate_csr.restype = ctypes.c_int
@@ -73,7 +74,7 @@ lib.cmrs_last_error.argtypes, lib.cmrs_last_error.restype = [], ctypes.c_char_p
 
 EXPORTED = ["cmrs_abi_version", "cmrs_num_strips", "cmrs_bits_for_height", "cmrs_from_csr_workspace",
             "cmrs_from_csr", "cmrs_to_csr_workspace", "cmrs_to_csr", "cmrs_spmv", "cmrs_validate_csr",
-            "cmrs_colblock_plan_bytes", "cmrs_colblock_plan", "cmrs_spmv_colblock",
+            "cmrs_colblock_plan_bytes", "cmrs_colblock_plan", "cmrs_spmv_colblock_workspace", "cmrs_spmv_colblock",
             "cmrs_status_string", "cmrs_last_error"]
 
 
@@ -247,8 +248,17 @@ def colblock_plan(A: CmrsMatrix, col_blocks: int, stream=None) -> ColblockPlan:
     return ColblockPlan(col_blocks, split)
 
 
+COLBLOCK_SCHEDULES = {"passes": 0, "concurrent": 1}
+
+
+def spmv_colblock_workspace_bytes(A: CmrsMatrix, col_blocks: int, schedule: str = "passes") -> int:
+    d = A.desc()
+    return int(lib.cmrs_spmv_colblock_workspace(ctypes.byref(d), col_blocks, COLBLOCK_SCHEDULES[schedule]))
+
+
 def spmv_colblock(A: CmrsMatrix, plan: ColblockPlan, x: torch.Tensor, out: torch.Tensor | None = None,
-                  variant: int | str = SPMV_AUTO, stream=None) -> torch.Tensor:
+                  variant: int | str = SPMV_AUTO, schedule: str = "passes", workspace: torch.Tensor | None = None,
+                  stream=None) -> torch.Tensor:
     """y = A x with the column-blocked schedule (A sorted)."""
     if isinstance(variant, str):
         variant = VARIANTS[variant]
@@ -260,9 +270,13 @@ def spmv_colblock(A: CmrsMatrix, plan: ColblockPlan, x: torch.Tensor, out: torch
     _dev(y, "y", xdt)
     if y.numel() != A.rows:
         raise ValueError("y has the wrong length")
+    wsb = spmv_colblock_workspace_bytes(A, plan.col_blocks, schedule)
+    if wsb and (workspace is None or workspace.numel() * workspace.element_size() < wsb):
+        workspace = torch.empty(wsb, dtype=torch.uint8, device=x.device)
     d = A.desc()
     st = lib.cmrs_spmv_colblock(ctypes.byref(d), _ptr(x), _ptr(y), _DT[xdt], int(variant), plan.col_blocks,
-                                _ptr(plan.split), plan.nbytes, _stream(stream))
+                                _ptr(plan.split), plan.nbytes, COLBLOCK_SCHEDULES[schedule],
+                                _ptr(workspace) if wsb else None, wsb, _stream(stream))
     _check(st, "cmrs_spmv_colblock")
     return y
 

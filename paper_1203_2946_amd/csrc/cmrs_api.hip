@@ -81,10 +81,8 @@ int32_t cmrs_bits_for_height(int32_t height) {
 }
 
 size_t cmrs_from_csr_workspace(int32_t rows, int32_t nnz, int32_t height, uint32_t flags) {
-    (void)rows;
-    (void)height;
-    if (!(flags & CMRS_SORT) || nnz <= 0) return 0;
-    return cmrs::from_csr_workspace_layout(nnz).total;
+    if (!(flags & CMRS_SORT) || nnz <= 0 || rows < 0 || height < 1) return 0;
+    return cmrs::from_csr_workspace_layout(rows, nnz, height).total;
 }
 
 cmrs_status_t cmrs_from_csr(int32_t rows, int32_t cols, int32_t nnz, const int32_t* row_ptr, const int32_t* col_ind,
@@ -204,14 +202,30 @@ cmrs_status_t cmrs_colblock_plan(const cmrs_mat_t* A, int32_t col_blocks, int32_
                     "cmrs_colblock_plan");
 }
 
+size_t cmrs_spmv_colblock_workspace(const cmrs_mat_t* A, int32_t col_blocks, int32_t schedule) {
+    if (!A || schedule != CMRS_COLBLOCK_CONCURRENT || col_blocks <= 1 || A->rows <= 0) return 0;
+    const size_t at = A->val_dtype == CMRS_R64F ? 8 : 4;
+    return static_cast<size_t>(col_blocks) * static_cast<size_t>(A->rows) * at;
+}
+
 cmrs_status_t cmrs_spmv_colblock(const cmrs_mat_t* A, const void* x, void* y, cmrs_dtype_t xy_dtype, int32_t variant,
-                                 int32_t col_blocks, const int32_t* split, size_t split_bytes, hipStream_t stream) {
+                                 int32_t col_blocks, const int32_t* split, size_t split_bytes, int32_t schedule,
+                                 void* workspace, size_t workspace_bytes, hipStream_t stream) {
     g_last_error[0] = 0;
     cmrs_status_t st = check_spmv_args(A, x, y, xy_dtype, variant);
     if (st != CMRS_OK || A->rows == 0) return st;
     st = check_colblock(A, col_blocks, split, split_bytes);
     if (st != CMRS_OK) return st;
-    return from_hip(cmrs::launch_spmv_colblock(A, x, y, variant, col_blocks, split, stream), "cmrs_spmv_colblock");
+    if (schedule != CMRS_COLBLOCK_PASSES && schedule != CMRS_COLBLOCK_CONCURRENT)
+        return fail(CMRS_ERR_INVALID_VALUE, "unknown schedule %d", schedule);
+    const size_t need = cmrs_spmv_colblock_workspace(A, col_blocks, schedule);
+    if (need > 0 && (!workspace || workspace_bytes < need))
+        return fail(CMRS_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace_bytes);
+    if (need > 0 && (ranges_overlap(workspace, need, y, cmrs::dtype_bytes(xy_dtype) * static_cast<size_t>(A->rows)) ||
+                     ranges_overlap(workspace, need, x, cmrs::dtype_bytes(xy_dtype) * static_cast<size_t>(A->cols))))
+        return fail(CMRS_ERR_INVALID_VALUE, "workspace overlaps x or y");
+    return from_hip(cmrs::launch_spmv_colblock(A, x, y, variant, col_blocks, split, schedule, workspace, stream),
+                    "cmrs_spmv_colblock");
 }
 
 cmrs_status_t cmrs_validate_csr(int32_t rows, int32_t cols, int32_t nnz, const int32_t* row_ptr,

@@ -31,12 +31,30 @@ constexpr int kWaveSortCap = 1024;
 constexpr int kBlockSortCap = 16384;
 
 struct FromCsrWorkspaceLayout {
-    size_t list_off;    // int32 count at offset 0, list of long strips at list_off
-    size_t list_cap;    // entries of the list
+    size_t small_off;   // int32 counts at offset 0 (short / long list), short-strip list at small_off
+    size_t small_cap;
+    size_t big_off;     // long-strip list
+    size_t big_cap;
     size_t global_off;  // uint64 sort area: 2*nnz entries
     size_t total;
 };
-FromCsrWorkspaceLayout from_csr_workspace_layout(int32_t nnz);
+FromCsrWorkspaceLayout from_csr_workspace_layout(int32_t rows, int32_t nnz, int32_t height);
+
+// Shape of the conversion group kernels: G lanes per strip and E = 8 entries
+// per lane, so that a group holds about 2.5 times the average strip where it
+// can (most strips then fit and take the fast path); G at least hb, since the strip's row
+// pointers sit one per lane of the group.
+struct ConvShape {
+    int g, e;
+};
+inline ConvShape conv_shape(int nnz, int strips, int hb) {
+    const double want = strips > 0 ? 2.5 * static_cast<double>(nnz) / strips : 0.0;
+    ConvShape s{2, 8};
+    while (s.g < 64 && s.g * s.e < want) s.g <<= 1;
+    if (s.g < hb) s.g = hb;
+    if (s.g < 2) s.g = 2;
+    return s;
+}
 
 hipError_t launch_from_csr(int32_t rows, int32_t cols, int32_t nnz, const int32_t* row_ptr,
                            const int32_t* col_ind, const void* val_in, cmrs_dtype_t dtype, int32_t height,
@@ -51,7 +69,7 @@ hipError_t launch_spmv(const cmrs_mat_t* A, const void* x, void* y, cmrs_dtype_t
 int resolve_spmv_variant(const cmrs_mat_t* A, int variant);
 hipError_t launch_colblock_plan(const cmrs_mat_t* A, int nb, int bw, int* split, hipStream_t stream);
 hipError_t launch_spmv_colblock(const cmrs_mat_t* A, const void* x, void* y, int variant, int nb, const int* split,
-                                hipStream_t stream);
+                                int schedule, void* workspace, hipStream_t stream);
 
 hipError_t launch_validate_csr(int32_t rows, int32_t cols, int32_t nnz, const int32_t* row_ptr,
                                const int32_t* col_ind, int32_t* flag, hipStream_t stream);

@@ -9,12 +9,22 @@
 // global scan is needed, a strip's entries are exactly its rows' entries), and
 // a stable scatter by RowInStrip restores row order.
 //
-// Work split: one 64-lane wave per strip.  The strip's height+1 row pointers
-// sit one per lane; the row of an entry is found with a binary search over
-// those lanes (cross-lane reads, no memory traffic).  Reordering sorts 64-bit
-// keys (word << 32 | position in strip), which makes the sort stable, with a
-// bitonic network: in the wave's LDS slice for strips of up to 1024 entries, in
-// a 1024-thread workgroup's LDS for up to 16384, in the workspace beyond that.
+// Work split.  The main kernels give each strip a group of G lanes (64/G
+// strips per wave) and each lane up to E = 8 entries, all loaded before any is
+// used, so a wave keeps 64*E entries of traffic in flight.  The row of
+// an entry comes from a binary search over the strip's row pointers, which sit
+// one per lane of the group (cross-lane reads, no memory traffic).
+//
+// Reorder: a strip of canonical CSR is `height` runs (its rows) that are
+// already sorted by column, and within a strip (column, RowInStrip) order is
+// the order of the packed words.  The runs are merged pairwise, log2(height)
+// levels, in LDS: each entry counts the keys of the partner run below its own
+// (binary search) and moves to its place in the merged run.  Keys are
+// (word << 32 | position in strip), unique, so the result is the stable order.
+// Strips that are longer than a group holds, or whose rows are not sorted,
+// go to a list in the workspace and are sorted by a bitonic network: in one
+// wave's LDS (up to 1024 entries), in a 1024-thread workgroup's LDS (up to
+// 16384), or in the workspace beyond that.
 #include <limits.h>
 
 #include "cmrs_device.hpp"
@@ -26,30 +36,20 @@ constexpr int kConvWaves = 4;
 constexpr int kConvThreads = kConvWaves * kWave;
 constexpr int kBlockSortThreads = 1024;
 
-__global__ void set_int_kernel(int32_t* p, int32_t v) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+__global__ void set_ints_kernel(int32_t* p, int32_t n, int32_t v) {
+    if (blockIdx.x == 0 && static_cast<int>(threadIdx.x) < n) p[threadIdx.x] = v;
 }
 
-// Sec. 3: StripPtr[j] = RowPtr[j*height] for j < strips, StripPtr[strips] = nnz.
-__global__ void strip_ptr_kernel(int strips, int height, int nnz, const int* __restrict__ row_ptr,
-                                 int* __restrict__ strip_ptr) {
-    const int j = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
-    if (j < strips)
-        strip_ptr[j] = row_ptr[j * height];
-    else if (j == strips)
-        strip_ptr[j] = nnz;
-}
-
-// Lane t (t <= nr) holds rp_t = RowPtr[first row of the strip + t]; lanes
-// above nr hold INT_MAX.  Returns the largest t with rp_t <= e, i.e. the
-// RowInStrip of entry e (empty rows are skipped because their rp_t repeats).
-// All lanes of the wave must be active.
+// Largest t with rp_t <= e, where lane base+t holds rp_t = RowPtr[first row of
+// the strip + t] (INT_MAX for rows the strip does not have): the RowInStrip of
+// entry e (empty rows are skipped because their rp_t repeats).  All lanes of
+// the wave must be active.
 template <int HB>
-__device__ inline int row_in_strip(int myrp, int e) {
+__device__ inline int row_in_strip(int myrp, int e, int base) {
     int lo = 0;
 #pragma unroll
     for (int step = HB / 2; step >= 1; step >>= 1) {
-        const int v = __shfl(myrp, lo + step);
+        const int v = __shfl(myrp, base + lo + step);
         if (v <= e) lo += step;
     }
     return lo;
@@ -59,7 +59,7 @@ struct StripRows {
     int r0, nr, myrp, s0, s1;
 };
 
-// Row pointers of strip `strip` spread over the wave's lanes.
+// Row pointers of strip `strip` spread over the lanes of the whole wave.
 __device__ inline StripRows load_strip_rows(int strip, int rows, int height, const int* __restrict__ row_ptr,
                                             int lane) {
     StripRows s;
@@ -69,29 +69,6 @@ __device__ inline StripRows load_strip_rows(int strip, int rows, int height, con
     s.s0 = __shfl(s.myrp, 0);
     s.s1 = __shfl(s.myrp, s.nr);
     return s;
-}
-
-// Unsorted conversion.  col_word may alias col_ind (in place); val_out may
-// alias val_in, in which case copy_val is 0.
-template <int HB, typename ET>
-__global__ __launch_bounds__(kConvThreads) void pack_kernel(int rows, int strips, int height, int bits,
-                                                            const int* __restrict__ row_ptr, const int* col_ind,
-                                                            const ET* val_in, uint32_t* col_word, ET* val_out,
-                                                            int copy_val) {
-    const int lane = lane_id();
-    const int wave = uniform(static_cast<int>(threadIdx.x) / kWave);
-    const int strip = xcd_logical_block(blockIdx.x, gridDim.x) * kConvWaves + wave;
-    if (strip >= strips) return;
-    const StripRows sr = load_strip_rows(strip, rows, height, row_ptr, lane);
-    for (int base = sr.s0; base < sr.s1; base += kWave) {
-        const int e = base + lane;
-        const int r = row_in_strip<HB>(sr.myrp, e);
-        if (e < sr.s1) {
-            const uint32_t c = static_cast<uint32_t>(col_ind[e]);
-            col_word[e] = (c << bits) | static_cast<uint32_t>(r);
-            if (copy_val) val_out[e] = val_in[e];
-        }
-    }
 }
 
 __device__ inline int pow2_at_least(int n) {
@@ -121,29 +98,50 @@ __device__ inline void bitonic_sort(uint64_t* k, int P, int tid, int nthreads, S
     }
 }
 
-// Sorted conversion, one wave per strip of at most kWaveSortCap entries;
-// longer strips are appended to the workspace list for the block kernel.
+// ------------------------------------------------------------------ whole-wave paths
+
+// Unsorted conversion of one strip by the whole wave, 8 loads per lane in
+// flight.
 template <int HB, typename ET>
-__global__ __launch_bounds__(kConvThreads) void sort_strips_wave_kernel(
-    int rows, int strips, int height, int bits, const int* __restrict__ row_ptr, const int* __restrict__ col_ind,
-    const ET* __restrict__ val_in, uint32_t* __restrict__ col_word, ET* __restrict__ val_out,
-    int* __restrict__ ws_count, int* __restrict__ ws_list) {
-    __shared__ uint64_t keys[kConvWaves][kWaveSortCap];
-    const int lane = lane_id();
-    const int wave = uniform(static_cast<int>(threadIdx.x) / kWave);
-    const int strip = xcd_logical_block(blockIdx.x, gridDim.x) * kConvWaves + wave;
-    if (strip >= strips) return;
+__device__ inline void pack_strip_wave(int strip, int rows, int height, int bits, const int* __restrict__ row_ptr,
+                                       const int* col_ind, const ET* val_in, uint32_t* col_word, ET* val_out,
+                                       int copy_val, int lane) {
+    constexpr int U = 8;
+    const StripRows sr = load_strip_rows(strip, rows, height, row_ptr, lane);
+    for (int base = sr.s0; base < sr.s1; base += U * kWave) {
+        int c[U];
+        ET v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = base + u * kWave + lane;
+            c[u] = e < sr.s1 ? col_ind[e] : 0;
+            v[u] = (e < sr.s1 && copy_val) ? val_in[e] : ET(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = base + u * kWave + lane;
+            const int r = row_in_strip<HB>(sr.myrp, e, 0);
+            if (e < sr.s1) {
+                col_word[e] = (static_cast<uint32_t>(c[u]) << bits) | static_cast<uint32_t>(r);
+                if (copy_val) val_out[e] = v[u];
+            }
+        }
+    }
+}
+
+// Sorted conversion of one strip of at most kWaveSortCap entries by the whole
+// wave, bitonic network in the wave's LDS slice k[kWaveSortCap].
+template <int HB, typename ET>
+__device__ inline void sort_strip_wave(int strip, int rows, int height, int bits, const int* __restrict__ row_ptr,
+                                       const int* __restrict__ col_ind, const ET* __restrict__ val_in,
+                                       uint32_t* __restrict__ col_word, ET* __restrict__ val_out, uint64_t* k,
+                                       int lane) {
     const StripRows sr = load_strip_rows(strip, rows, height, row_ptr, lane);
     const int n = sr.s1 - sr.s0;
-    if (n > kWaveSortCap) {
-        if (lane == 0) ws_list[atomicAdd(ws_count, 1)] = strip;
-        return;
-    }
-    uint64_t* k = keys[wave];
     const int P = pow2_at_least(n);
     for (int base = 0; base < P; base += kWave) {
         const int i = base + lane;
-        const int r = row_in_strip<HB>(sr.myrp, sr.s0 + i);
+        const int r = row_in_strip<HB>(sr.myrp, sr.s0 + i, 0);
         if (i < n) {
             const uint32_t w = (static_cast<uint32_t>(col_ind[sr.s0 + i]) << bits) | static_cast<uint32_t>(r);
             k[i] = (static_cast<uint64_t>(w) << 32) | static_cast<uint32_t>(i);
@@ -158,21 +156,415 @@ __global__ __launch_bounds__(kConvThreads) void sort_strips_wave_kernel(
         col_word[sr.s0 + i] = static_cast<uint32_t>(kk >> 32);
         val_out[sr.s0 + i] = val_in[sr.s0 + static_cast<int>(static_cast<uint32_t>(kk))];
     }
+    wave_lds_sync();
 }
 
-// Sorted conversion of the long strips listed by the wave kernel: one
-// 1024-thread workgroup per strip, strips taken in a grid-stride loop.
+// CMRS -> CSR of one strip by the whole wave (two passes over the strip, 4
+// loads per lane in flight).
 template <int HB, typename ET>
-__global__ __launch_bounds__(kBlockSortThreads) void sort_strips_block_kernel(
+__device__ inline void to_csr_strip_wave(int strip, int rows, int strips, int height, int bits,
+                                         const int* __restrict__ strip_ptr, const uint32_t* __restrict__ word,
+                                         const ET* __restrict__ val, int* __restrict__ row_ptr,
+                                         int* __restrict__ col_ind, ET* __restrict__ val_out, int lane) {
+    constexpr int U = 4;
+    const int r0 = strip * height;
+    const int nr = min(height, rows - r0);
+    const int s0 = strip_ptr[strip], s1 = strip_ptr[strip + 1];
+    const uint32_t mask = (1u << bits) - 1u;
+    // Pass 1: lane t counts the entries whose RowInStrip is t.
+    int cnt = 0;
+    for (int b0 = s0; b0 < s1; b0 += U * kWave) {
+        uint32_t r[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = b0 + u * kWave + lane;
+            r[u] = e < s1 ? (word[e] & mask) : 0xffffffffu;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll 4
+            for (int t = 0; t < HB; ++t) {
+                const uint64_t m = ballot(r[u] == static_cast<uint32_t>(t));
+                if (lane == t) cnt += __popcll(m);
+            }
+        }
+    }
+    // Exclusive prefix over lanes: the CSR position of each row's first entry.
+    int incl = cnt;
+#pragma unroll
+    for (int off = 1; off < HB; off <<= 1) {
+        const int v = __shfl_up(incl, off);
+        if (lane >= off) incl += v;
+    }
+    const int start = s0 + incl - cnt;
+    if (lane < nr) row_ptr[r0 + lane] = start;
+    if (strip == strips - 1 && lane == 0) row_ptr[rows] = s1;
+    // Pass 2: stable scatter; lane t tracks the next free slot of row t.
+    int next = start;
+    for (int b0 = s0; b0 < s1; b0 += U * kWave) {
+        uint32_t w[U];
+        ET v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = b0 + u * kWave + lane;
+            w[u] = e < s1 ? word[e] : 0u;
+            v[u] = e < s1 ? val[e] : ET(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = b0 + u * kWave + lane;
+            const bool act = e < s1;
+            const uint32_t r = act ? (w[u] & mask) : 0xffffffffu;
+            int pos = 0;
+#pragma unroll 4
+            for (int t = 0; t < HB; ++t) {
+                const uint64_t m = ballot(r == static_cast<uint32_t>(t));
+                const int base_t = __shfl(next, t);
+                if (r == static_cast<uint32_t>(t)) pos = base_t + __popcll(m & lanemask_lt());
+                if (lane == t) next += __popcll(m);
+            }
+            if (act && r < static_cast<uint32_t>(nr)) {
+                col_ind[pos] = static_cast<int>(w[u] >> bits);
+                val_out[pos] = v[u];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ group kernels
+
+__device__ inline uint64_t group_mask(int gbase, int G) {
+    return G == kWave ? ~0ull : (((1ull << G) - 1ull) << gbase);
+}
+
+// Number of per-lane slots any group of the wave uses: ceil(max n / G)
+// (wave-uniform), so the slot loops stop at the longest strip of the wave.
+template <int G>
+__device__ inline int used_slots(int n) {
+    int m = n;
+#pragma unroll
+    for (int off = kWave / 2; off >= G; off >>= 1) m = max(m, __shfl_xor(m, off));
+    return uniform((m + G - 1) / G);
+}
+
+// CSR -> CMRS for strips of at most G*E entries, G lanes per strip.
+// Writes strip_ptr too.  Unsorted: longer strips are packed by the whole
+// wave afterwards.  Sorted: longer or unsorted-row strips go to the workspace
+// lists (ws_count[0] / ws_small: at most kWaveSortCap entries; ws_count[1] /
+// ws_big: longer).  col_word may alias col_ind and val_out may alias val_in
+// only when unsorted.
+template <int HB, int G, int E, bool SORT, typename ET>
+__global__ __launch_bounds__(kConvThreads) void from_csr_group_kernel(
+    int rows, int strips, int height, int bits, int nnz, const int* __restrict__ row_ptr, const int* col_ind,
+    const ET* val_in, int* __restrict__ strip_ptr, uint32_t* col_word, ET* val_out, int copy_val,
+    int* __restrict__ ws_count, int* __restrict__ ws_small, int* __restrict__ ws_big) {
+    static_assert(G >= HB && G <= kWave && G >= 2, "group width");
+    constexpr int NG = kWave / G;
+    constexpr int CAP = G * E;
+    __shared__ uint64_t lds[SORT ? kConvWaves : 1][SORT ? 2 * kWave * E : 1];
+    const int lane = lane_id();
+    const int wave = uniform(static_cast<int>(threadIdx.x) / kWave);
+    const int strip0 = (xcd_logical_block(blockIdx.x, gridDim.x) * kConvWaves + wave) * NG;
+    if (strip0 >= strips) return;
+    const int g = lane / G, q = lane % G, gbase = g * G;
+    const int strip = strip0 + g;
+    const bool valid = strip < strips;
+    const int r0 = strip * height;
+    const int nr = valid ? min(height, rows - r0) : 0;
+    const int myrp = (valid && q < nr) ? row_ptr[r0 + q] : INT_MAX;
+    const int s1 = valid ? row_ptr[r0 + nr] : 0;
+    const int s0_lane = __shfl(myrp, gbase);
+    const int s0 = valid ? s0_lane : 0;
+    const int n = s1 - s0;
+    if (valid && q == 0) {
+        strip_ptr[strip] = s0;
+        if (strip == strips - 1) strip_ptr[strips] = nnz;
+    }
+    bool special = valid && n > CAP;
+    const int umax = used_slots<G>(valid && !special ? n : 0);
+
+    int c[E], t[E];
+    ET v[E];
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+        c[u] = 0;
+        t[u] = 0;
+        v[u] = ET(0);
+        if (u < umax) {
+            const int j = s0 + q + G * u;
+            const bool act = valid && !special && j < s1;
+            if (act) {
+                c[u] = col_ind[j];
+                v[u] = val_in[j];
+            }
+            t[u] = row_in_strip<HB>(myrp, j, gbase);
+        }
+    }
+
+    if constexpr (!SORT) {
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            const int j = s0 + q + G * u;
+            if (u < umax && valid && !special && j < s1) {
+                col_word[j] = (static_cast<uint32_t>(c[u]) << bits) | static_cast<uint32_t>(t[u]);
+                if (copy_val) val_out[j] = v[u];
+            }
+        }
+        uint64_t longs = ballot(special && q == 0);
+        while (longs) {
+            const int leader = __ffsll(static_cast<unsigned long long>(longs)) - 1;
+            longs &= longs - 1;
+            pack_strip_wave<HB, ET>(strip0 + leader / G, rows, height, bits, row_ptr, col_ind, val_in, col_word,
+                                    val_out, copy_val, lane);
+        }
+        return;
+    } else {
+        // Rows must ascend (non-strictly) by column for the merge.
+        bool bad = false;
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            if (u >= umax) break;
+            const int j = s0 + q + G * u;
+            const int c_right = __shfl(c[u], lane + 1 < kWave ? lane + 1 : lane);
+            const int c_wrap = __shfl(c[u + 1 < E ? u + 1 : u], gbase);
+            const int cn = q + 1 < G ? c_right : c_wrap;
+            const int tn = t[u] + 1;
+            const int rpn_lane = __shfl(myrp, gbase + (tn < G ? tn : G - 1));
+            const int rpn = tn < nr ? rpn_lane : s1;
+            const bool act = valid && !special && j < s1;
+            // j + 1 < rpn: the next entry exists and lies in the same row (u + 1 < E
+            // whenever q == G - 1, because the strip holds at most G*E entries).
+            if (act && j + 1 < rpn && cn < c[u]) bad = true;
+        }
+        const bool gbad = (ballot(bad) & group_mask(gbase, G)) != 0;
+        special = special || (valid && gbad);
+        if (valid && special && q == 0) {
+            if (n <= kWaveSortCap)
+                ws_small[atomicAdd(&ws_count[0], 1)] = strip;
+            else
+                ws_big[atomicAdd(&ws_count[1], 1)] = strip;
+        }
+        const bool go = valid && !special;
+        uint64_t* A = &lds[wave][gbase * E];
+        uint64_t* B = &lds[wave][kWave * E + gbase * E];
+        uint64_t key[E];
+        int pos[E];
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            if (u >= umax) break;
+            const int p = q + G * u;
+            const uint32_t w = (static_cast<uint32_t>(c[u]) << bits) | static_cast<uint32_t>(t[u]);
+            key[u] = (static_cast<uint64_t>(w) << 32) | static_cast<uint32_t>(p);
+            pos[u] = p;
+            if (go && p < n) A[p] = key[u];
+        }
+        // Strip-relative row pointer of strip row x, 0 <= x <= HB (all lanes active).
+        auto rp = [&](int x) {
+            const int lv = __shfl(myrp, gbase + (x < G ? x : G - 1));
+            return (x < nr ? lv : s1) - s0;
+        };
+#pragma unroll 1
+        for (int k = 0; (1 << k) < HB; ++k) {
+            wave_lds_sync();
+#pragma unroll
+            for (int u = 0; u < E; ++u) {
+                if (u >= umax) break;
+                const int run = t[u] >> k;
+                const int partner = run ^ 1;
+                const int run_lo = rp(run << k);
+                const int merged_lo = rp((run & ~1) << k);
+                const int p_lo = rp(partner << k);
+                const int p_hi = rp((partner + 1) << k);
+                if (go && q + G * u < n) {
+                    int a = p_lo, len = p_hi - p_lo;
+                    while (len > 0) {
+                        const int half = len >> 1;
+                        if (A[a + half] < key[u]) {
+                            a += half + 1;
+                            len -= half + 1;
+                        } else {
+                            len = half;
+                        }
+                    }
+                    pos[u] = merged_lo + (pos[u] - run_lo) + (a - p_lo);
+                    B[pos[u]] = key[u];
+                }
+            }
+            uint64_t* tmp = A;
+            A = B;
+            B = tmp;
+        }
+        wave_lds_sync();
+        // Values by original position into the free buffer, then out in sorted order.
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            if (u >= umax) break;
+            const int p = q + G * u;
+            if (go && p < n) B[p] = static_cast<uint64_t>(v[u]);
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            if (u >= umax) break;
+            const int i = q + G * u;
+            if (go && i < n) {
+                const uint64_t kk = A[i];
+                col_word[s0 + i] = static_cast<uint32_t>(kk >> 32);
+                val_out[s0 + i] = static_cast<ET>(B[static_cast<uint32_t>(kk)]);
+            }
+        }
+    }
+}
+
+// CMRS -> CSR for strips of at most G*E entries, G lanes per strip;
+// longer strips by the whole wave afterwards.
+template <int HB, int G, int E, typename ET>
+__global__ __launch_bounds__(kConvThreads) void to_csr_group_kernel(
+    int rows, int strips, int height, int bits, const int* __restrict__ strip_ptr,
+    const uint32_t* __restrict__ word, const ET* __restrict__ val, int* __restrict__ row_ptr,
+    int* __restrict__ col_ind, ET* __restrict__ val_out) {
+    static_assert(G >= HB && G <= kWave && G >= 2, "group width");
+    constexpr int NG = kWave / G;
+    constexpr int CAP = G * E;
+    const int lane = lane_id();
+    const int wave = uniform(static_cast<int>(threadIdx.x) / kWave);
+    const int strip0 = (xcd_logical_block(blockIdx.x, gridDim.x) * kConvWaves + wave) * NG;
+    if (strip0 >= strips) return;
+    const int g = lane / G, q = lane % G, gbase = g * G;
+    const int strip = strip0 + g;
+    const bool valid = strip < strips;
+    const int s0 = valid ? strip_ptr[strip] : 0;
+    const int s1 = valid ? strip_ptr[strip + 1] : 0;
+    const int n = s1 - s0;
+    const int r0 = strip * height;
+    const int nr = valid ? min(height, rows - r0) : 0;
+    const bool is_long = valid && n > CAP;
+    const bool go = valid && !is_long;
+    const uint32_t mask = (1u << bits) - 1u;
+    const uint64_t gm = group_mask(gbase, G);
+    const uint64_t lt = lanemask_lt();
+
+    const int umax = used_slots<G>(go ? n : 0);
+    uint32_t w[E], r[E];
+    ET v[E];
+    int rank[E];
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+        w[u] = 0u;
+        v[u] = ET(0);
+        r[u] = 0xffffffffu;
+        rank[u] = 0;
+        if (u < umax) {
+            const int j = s0 + q + G * u;
+            if (go && j < s1) {
+                w[u] = word[j];
+                v[u] = val[j];
+                r[u] = w[u] & mask;
+            }
+        }
+    }
+    int start;  // lane gbase + rr (rr < HB): CSR position of the first entry of row rr
+    if constexpr (G == kWave && HB <= 8) {
+        // One strip per wave: the per-row counters are wave-uniform.
+        int running[HB];
+#pragma unroll
+        for (int rr = 0; rr < HB; ++rr) running[rr] = 0;
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            if (u >= umax) break;
+#pragma unroll
+            for (int rr = 0; rr < HB; ++rr) {
+                const uint64_t m = ballot(r[u] == static_cast<uint32_t>(rr));
+                if (r[u] == static_cast<uint32_t>(rr)) rank[u] = running[rr] + __popcll(m & lt);
+                running[rr] += __popcll(m);
+            }
+        }
+        int acc = s0;
+        start = s0;
+#pragma unroll
+        for (int rr = 0; rr < HB; ++rr) {
+            if (q == rr) start = acc;
+            acc += running[rr];
+        }
+    } else {
+        int running = 0;  // lane gbase + rr: entries of RowInStrip rr seen so far
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            if (u >= umax) break;
+#pragma unroll 1
+            for (int rr = 0; rr < HB; ++rr) {
+                const uint64_t m = ballot(r[u] == static_cast<uint32_t>(rr)) & gm;
+                const int before = __shfl(running, gbase + rr);
+                if (r[u] == static_cast<uint32_t>(rr)) rank[u] = before + __popcll(m & lt);
+                if (q == rr) running += __popcll(m);
+            }
+        }
+        // Exclusive prefix of the per-row counts inside the group.
+        const int cnt = q < HB ? running : 0;
+        int incl = cnt;
+#pragma unroll
+        for (int off = 1; off < HB; off <<= 1) {
+            const int sv = __shfl_up(incl, off, G);
+            if (q >= off) incl += sv;
+        }
+        start = s0 + incl - cnt;
+    }
+    if (go && q < nr) row_ptr[r0 + q] = start;
+    if (valid && strip == strips - 1 && q == 0) row_ptr[rows] = s1;
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+        if (u >= umax) break;
+        const int j = s0 + q + G * u;
+        const int base = __shfl(start, gbase + static_cast<int>(r[u] & (HB - 1)));
+        // r < nr holds for every valid word; the guard keeps an invalid one from
+        // writing outside this strip's range [s0, s1).
+        if (go && j < s1 && r[u] < static_cast<uint32_t>(nr)) {
+            const int p = base + rank[u];
+            col_ind[p] = static_cast<int>(w[u] >> bits);
+            val_out[p] = v[u];
+        }
+    }
+    uint64_t longs = ballot(is_long && q == 0);
+    while (longs) {
+        const int leader = __ffsll(static_cast<unsigned long long>(longs)) - 1;
+        longs &= longs - 1;
+        to_csr_strip_wave<HB, ET>(strip0 + leader / G, rows, strips, height, bits, strip_ptr, word, val, row_ptr,
+                                  col_ind, val_out, lane);
+    }
+}
+
+// ------------------------------------------------------------------ list kernels
+
+// Sorted conversion of the listed strips of at most kWaveSortCap entries: one
+// wave per strip, strips taken in a grid-stride loop.
+template <int HB, typename ET>
+__global__ __launch_bounds__(kConvThreads) void sort_list_wave_kernel(
     int rows, int height, int bits, const int* __restrict__ row_ptr, const int* __restrict__ col_ind,
     const ET* __restrict__ val_in, uint32_t* __restrict__ col_word, ET* __restrict__ val_out,
-    const int* __restrict__ ws_count, const int* __restrict__ ws_list, uint64_t* __restrict__ gkeys) {
+    const int* __restrict__ ws_count, const int* __restrict__ ws_small) {
+    __shared__ uint64_t keys[kConvWaves][kWaveSortCap];
+    const int lane = lane_id();
+    const int wave = uniform(static_cast<int>(threadIdx.x) / kWave);
+    const int count = ws_count[0];
+    const int nwaves = static_cast<int>(gridDim.x) * kConvWaves;
+    for (int item = static_cast<int>(blockIdx.x) * kConvWaves + wave; item < count; item += nwaves)
+        sort_strip_wave<HB, ET>(ws_small[item], rows, height, bits, row_ptr, col_ind, val_in, col_word, val_out,
+                                keys[wave], lane);
+}
+
+// Sorted conversion of the listed long strips: one 1024-thread workgroup per
+// strip, strips taken in a grid-stride loop.
+template <int HB, typename ET>
+__global__ __launch_bounds__(kBlockSortThreads) void sort_list_block_kernel(
+    int rows, int height, int bits, const int* __restrict__ row_ptr, const int* __restrict__ col_ind,
+    const ET* __restrict__ val_in, uint32_t* __restrict__ col_word, ET* __restrict__ val_out,
+    const int* __restrict__ ws_count, const int* __restrict__ ws_big, uint64_t* __restrict__ gkeys) {
     __shared__ uint64_t skeys[kBlockSortCap];
     const int lane = lane_id();
     const int wave = static_cast<int>(threadIdx.x) / kWave;
-    const int count = *ws_count;
+    const int count = ws_count[1];
     for (int item = blockIdx.x; item < count; item += gridDim.x) {
-        const int strip = ws_list[item];
+        const int strip = ws_big[item];
         const StripRows sr = load_strip_rows(strip, rows, height, row_ptr, lane);
         const int n = sr.s1 - sr.s0;
         const int P = pow2_at_least(n);
@@ -181,7 +573,7 @@ __global__ __launch_bounds__(kBlockSortThreads) void sort_strips_block_kernel(
         uint64_t* k = in_lds ? skeys : gkeys + 2 * static_cast<size_t>(sr.s0);
         for (int base = wave * kWave; base < P; base += kBlockSortThreads) {
             const int i = base + lane;
-            const int r = row_in_strip<HB>(sr.myrp, sr.s0 + i);
+            const int r = row_in_strip<HB>(sr.myrp, sr.s0 + i, 0);
             if (i < n) {
                 const uint32_t w = (static_cast<uint32_t>(col_ind[sr.s0 + i]) << bits) | static_cast<uint32_t>(r);
                 k[i] = (static_cast<uint64_t>(w) << 32) | static_cast<uint32_t>(i);
@@ -209,66 +601,6 @@ __global__ __launch_bounds__(kBlockSortThreads) void sort_strips_block_kernel(
     }
 }
 
-// CMRS -> CSR, one wave per strip.
-template <int HB, typename ET>
-__global__ __launch_bounds__(kConvThreads) void to_csr_kernel(int rows, int strips, int height, int bits,
-                                                              const int* __restrict__ strip_ptr,
-                                                              const uint32_t* __restrict__ word,
-                                                              const ET* __restrict__ val, int* __restrict__ row_ptr,
-                                                              int* __restrict__ col_ind, ET* __restrict__ val_out) {
-    const int lane = lane_id();
-    const int wave = uniform(static_cast<int>(threadIdx.x) / kWave);
-    const int strip = xcd_logical_block(blockIdx.x, gridDim.x) * kConvWaves + wave;
-    if (strip >= strips) return;
-    const int r0 = strip * height;
-    const int nr = min(height, rows - r0);
-    const int s0 = strip_ptr[strip], s1 = strip_ptr[strip + 1];
-    const uint32_t mask = (1u << bits) - 1u;
-
-    // Pass 1: lane t counts the entries whose RowInStrip is t.
-    int cnt = 0;
-    for (int base = s0; base < s1; base += kWave) {
-        const int e = base + lane;
-        const uint32_t r = e < s1 ? (word[e] & mask) : 0xffffffffu;
-#pragma unroll
-        for (int t = 0; t < HB; ++t) {
-            const uint64_t m = ballot(r == static_cast<uint32_t>(t));
-            if (lane == t) cnt += __popcll(m);
-        }
-    }
-    // Exclusive prefix over lanes: the CSR position of each row's first entry.
-    int incl = cnt;
-#pragma unroll
-    for (int off = 1; off < HB; off <<= 1) {
-        const int v = __shfl_up(incl, off);
-        if (lane >= off) incl += v;
-    }
-    const int start = s0 + incl - cnt;
-    if (lane < nr) row_ptr[r0 + lane] = start;
-    if (strip == strips - 1 && lane == 0) row_ptr[rows] = s1;
-
-    // Pass 2: stable scatter; lane t tracks the next free slot of row t.
-    int next = start;
-    for (int base = s0; base < s1; base += kWave) {
-        const int e = base + lane;
-        const bool act = e < s1;
-        const uint32_t w = act ? word[e] : 0u;
-        const uint32_t r = act ? (w & mask) : 0xffffffffu;
-        int pos = 0;
-#pragma unroll
-        for (int t = 0; t < HB; ++t) {
-            const uint64_t m = ballot(r == static_cast<uint32_t>(t));
-            const int base_t = __shfl(next, t);
-            if (r == static_cast<uint32_t>(t)) pos = base_t + __popcll(m & lanemask_lt());
-            if (lane == t) next += __popcll(m);
-        }
-        if (act) {
-            col_ind[pos] = static_cast<int>(w >> bits);
-            val_out[pos] = val[e];
-        }
-    }
-}
-
 __global__ void validate_csr_kernel(int rows, int cols, int nnz, const int* __restrict__ row_ptr,
                                     const int* __restrict__ col_ind, int* __restrict__ flag) {
     const int tid = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
@@ -288,76 +620,130 @@ namespace {
 
 inline size_t align256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 
-template <typename ET, int HB>
-hipError_t from_csr_hb(int rows, int nnz, const int* row_ptr, const int* col_ind, const void* val_in, int height,
-                       int bits, uint32_t flags, uint32_t* col_word, void* val_out, void* workspace,
-                       hipStream_t stream) {
-    const int strips = (rows + height - 1) / height;
-    const int blocks = (strips + kConvWaves - 1) / kConvWaves;
+struct Conv {
+    int rows, strips, height, bits, nnz;
+};
+
+template <int G, int E, int HB, typename ET>
+hipError_t from_csr_g(const Conv& cv, uint32_t flags, const int* row_ptr, const int* col_ind, const void* val_in,
+                      int* strip_ptr, uint32_t* col_word, void* val_out, void* workspace, hipStream_t stream) {
+    constexpr int NG = kWave / G;
+    const int waves = (cv.strips + NG - 1) / NG;
+    const int blocks = (waves + kConvWaves - 1) / kConvWaves;
     const auto* vin = static_cast<const ET*>(val_in);
     auto* vout = static_cast<ET*>(val_out);
     if (!(flags & CMRS_SORT)) {
-        hipLaunchKernelGGL((pack_kernel<HB, ET>), dim3(blocks), dim3(kConvThreads), 0, stream, rows, strips, height,
-                           bits, row_ptr, col_ind, vin, col_word, vout, val_out != val_in ? 1 : 0);
+        hipLaunchKernelGGL((from_csr_group_kernel<HB, G, E, false, ET>), dim3(blocks), dim3(kConvThreads), 0, stream,
+                           cv.rows, cv.strips, cv.height, cv.bits, cv.nnz, row_ptr, col_ind, vin, strip_ptr, col_word,
+                           vout, val_out != val_in ? 1 : 0, nullptr, nullptr, nullptr);
         return hipGetLastError();
     }
-    const FromCsrWorkspaceLayout L = from_csr_workspace_layout(nnz);
+    const FromCsrWorkspaceLayout L = from_csr_workspace_layout(cv.rows, cv.nnz, cv.height);
     auto* ws = static_cast<char*>(workspace);
     int* ws_count = reinterpret_cast<int*>(ws);
-    int* ws_list = reinterpret_cast<int*>(ws + L.list_off);
+    int* ws_small = reinterpret_cast<int*>(ws + L.small_off);
+    int* ws_big = reinterpret_cast<int*>(ws + L.big_off);
     auto* gkeys = reinterpret_cast<uint64_t*>(ws + L.global_off);
-    hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, stream, ws_count, 0);
-    hipLaunchKernelGGL((sort_strips_wave_kernel<HB, ET>), dim3(blocks), dim3(kConvThreads), 0, stream, rows,
-                       strips, height, bits, row_ptr, col_ind, vin, col_word, vout, ws_count, ws_list);
-    const int grid2 = static_cast<int>(L.list_cap < 512 ? L.list_cap : 512);
-    hipLaunchKernelGGL((sort_strips_block_kernel<HB, ET>), dim3(grid2), dim3(kBlockSortThreads), 0, stream, rows,
-                       height, bits, row_ptr, col_ind, vin, col_word, vout, ws_count, ws_list, gkeys);
+    hipLaunchKernelGGL(set_ints_kernel, dim3(1), dim3(64), 0, stream, ws_count, 2, 0);
+    hipLaunchKernelGGL((from_csr_group_kernel<HB, G, E, true, ET>), dim3(blocks), dim3(kConvThreads), 0, stream,
+                       cv.rows, cv.strips, cv.height, cv.bits, cv.nnz, row_ptr, col_ind, vin, strip_ptr, col_word,
+                       vout, 1, ws_count, ws_small, ws_big);
+    const size_t small_blocks = (L.small_cap + kConvWaves - 1) / kConvWaves;
+    const int g1 = static_cast<int>(small_blocks < 1024 ? small_blocks : 1024);
+    hipLaunchKernelGGL((sort_list_wave_kernel<HB, ET>), dim3(g1), dim3(kConvThreads), 0, stream, cv.rows, cv.height,
+                       cv.bits, row_ptr, col_ind, vin, col_word, vout, ws_count, ws_small);
+    const int g2 = static_cast<int>(L.big_cap < 512 ? L.big_cap : 512);
+    hipLaunchKernelGGL((sort_list_block_kernel<HB, ET>), dim3(g2), dim3(kBlockSortThreads), 0, stream, cv.rows,
+                       cv.height, cv.bits, row_ptr, col_ind, vin, col_word, vout, ws_count, ws_big, gkeys);
     return hipGetLastError();
+}
+
+template <int HB, typename ET>
+hipError_t from_csr_hb(const Conv& cv, uint32_t flags, const int* row_ptr, const int* col_ind, const void* val_in,
+                       int* strip_ptr, uint32_t* col_word, void* val_out, void* workspace, hipStream_t stream) {
+    const ConvShape sh = conv_shape(cv.nnz, cv.strips, HB);
+#define CMRS_FROM_G(GG, EE)                                                                                      \
+    if constexpr (GG >= HB) {                                                                                    \
+        if (sh.g == GG && sh.e == EE)                                                                            \
+            return from_csr_g<GG, EE, HB, ET>(cv, flags, row_ptr, col_ind, val_in, strip_ptr, col_word, val_out, \
+                                              workspace, stream);                                                \
+    }
+    CMRS_FROM_G(2, 8)
+    CMRS_FROM_G(4, 8)
+    CMRS_FROM_G(8, 8)
+    CMRS_FROM_G(16, 8)
+    CMRS_FROM_G(32, 8)
+    CMRS_FROM_G(64, 8)
+#undef CMRS_FROM_G
+    return hipErrorInvalidValue;
 }
 
 template <typename ET>
-hipError_t from_csr_typed(int rows, int nnz, const int* row_ptr, const int* col_ind, const void* val_in, int height,
-                          int bits, uint32_t flags, uint32_t* col_word, void* val_out, void* workspace,
+hipError_t from_csr_typed(const Conv& cv, uint32_t flags, const int* row_ptr, const int* col_ind,
+                          const void* val_in, int* strip_ptr, uint32_t* col_word, void* val_out, void* workspace,
                           hipStream_t stream) {
-    switch (next_pow2(height)) {
-        case 1: return from_csr_hb<ET, 1>(rows, nnz, row_ptr, col_ind, val_in, height, bits, flags, col_word, val_out, workspace, stream);
-        case 2: return from_csr_hb<ET, 2>(rows, nnz, row_ptr, col_ind, val_in, height, bits, flags, col_word, val_out, workspace, stream);
-        case 4: return from_csr_hb<ET, 4>(rows, nnz, row_ptr, col_ind, val_in, height, bits, flags, col_word, val_out, workspace, stream);
-        case 8: return from_csr_hb<ET, 8>(rows, nnz, row_ptr, col_ind, val_in, height, bits, flags, col_word, val_out, workspace, stream);
-        case 16: return from_csr_hb<ET, 16>(rows, nnz, row_ptr, col_ind, val_in, height, bits, flags, col_word, val_out, workspace, stream);
-        default: return from_csr_hb<ET, 32>(rows, nnz, row_ptr, col_ind, val_in, height, bits, flags, col_word, val_out, workspace, stream);
+    switch (next_pow2(cv.height)) {
+        case 1: return from_csr_hb<1, ET>(cv, flags, row_ptr, col_ind, val_in, strip_ptr, col_word, val_out, workspace, stream);
+        case 2: return from_csr_hb<2, ET>(cv, flags, row_ptr, col_ind, val_in, strip_ptr, col_word, val_out, workspace, stream);
+        case 4: return from_csr_hb<4, ET>(cv, flags, row_ptr, col_ind, val_in, strip_ptr, col_word, val_out, workspace, stream);
+        case 8: return from_csr_hb<8, ET>(cv, flags, row_ptr, col_ind, val_in, strip_ptr, col_word, val_out, workspace, stream);
+        case 16: return from_csr_hb<16, ET>(cv, flags, row_ptr, col_ind, val_in, strip_ptr, col_word, val_out, workspace, stream);
+        default: return from_csr_hb<32, ET>(cv, flags, row_ptr, col_ind, val_in, strip_ptr, col_word, val_out, workspace, stream);
     }
 }
 
-template <typename ET, int HB>
+template <int G, int E, int HB, typename ET>
+hipError_t to_csr_g(const cmrs_mat_t* A, int strips, int* row_ptr, int* col_ind, void* val_out, hipStream_t stream) {
+    constexpr int NG = kWave / G;
+    const int waves = (strips + NG - 1) / NG;
+    const int blocks = (waves + kConvWaves - 1) / kConvWaves;
+    hipLaunchKernelGGL((to_csr_group_kernel<HB, G, E, ET>), dim3(blocks), dim3(kConvThreads), 0, stream, A->rows,
+                       strips, A->height, A->bits, A->strip_ptr, A->col_word, static_cast<const ET*>(A->val),
+                       row_ptr, col_ind, static_cast<ET*>(val_out));
+    return hipGetLastError();
+}
+
+template <int HB, typename ET>
 hipError_t to_csr_hb(const cmrs_mat_t* A, int* row_ptr, int* col_ind, void* val_out, hipStream_t stream) {
     const int strips = (A->rows + A->height - 1) / A->height;
-    const int blocks = (strips + kConvWaves - 1) / kConvWaves;
-    hipLaunchKernelGGL((to_csr_kernel<HB, ET>), dim3(blocks), dim3(kConvThreads), 0, stream, A->rows, strips,
-                       A->height, A->bits, A->strip_ptr, A->col_word, static_cast<const ET*>(A->val), row_ptr,
-                       col_ind, static_cast<ET*>(val_out));
-    return hipGetLastError();
+    const ConvShape sh = conv_shape(A->nnz, strips, HB);
+#define CMRS_TO_G(GG, EE)                                                                         \
+    if constexpr (GG >= HB) {                                                                     \
+        if (sh.g == GG && sh.e == EE)                                                             \
+            return to_csr_g<GG, EE, HB, ET>(A, strips, row_ptr, col_ind, val_out, stream);        \
+    }
+    CMRS_TO_G(2, 8)
+    CMRS_TO_G(4, 8)
+    CMRS_TO_G(8, 8)
+    CMRS_TO_G(16, 8)
+    CMRS_TO_G(32, 8)
+    CMRS_TO_G(64, 8)
+#undef CMRS_TO_G
+    return hipErrorInvalidValue;
 }
 
 template <typename ET>
 hipError_t to_csr_typed(const cmrs_mat_t* A, int* row_ptr, int* col_ind, void* val_out, hipStream_t stream) {
     switch (next_pow2(A->height)) {
-        case 1: return to_csr_hb<ET, 1>(A, row_ptr, col_ind, val_out, stream);
-        case 2: return to_csr_hb<ET, 2>(A, row_ptr, col_ind, val_out, stream);
-        case 4: return to_csr_hb<ET, 4>(A, row_ptr, col_ind, val_out, stream);
-        case 8: return to_csr_hb<ET, 8>(A, row_ptr, col_ind, val_out, stream);
-        case 16: return to_csr_hb<ET, 16>(A, row_ptr, col_ind, val_out, stream);
-        default: return to_csr_hb<ET, 32>(A, row_ptr, col_ind, val_out, stream);
+        case 1: return to_csr_hb<1, ET>(A, row_ptr, col_ind, val_out, stream);
+        case 2: return to_csr_hb<2, ET>(A, row_ptr, col_ind, val_out, stream);
+        case 4: return to_csr_hb<4, ET>(A, row_ptr, col_ind, val_out, stream);
+        case 8: return to_csr_hb<8, ET>(A, row_ptr, col_ind, val_out, stream);
+        case 16: return to_csr_hb<16, ET>(A, row_ptr, col_ind, val_out, stream);
+        default: return to_csr_hb<32, ET>(A, row_ptr, col_ind, val_out, stream);
     }
 }
 
 }  // namespace
 
-FromCsrWorkspaceLayout from_csr_workspace_layout(int32_t nnz) {
+FromCsrWorkspaceLayout from_csr_workspace_layout(int32_t rows, int32_t nnz, int32_t height) {
     FromCsrWorkspaceLayout L;
-    L.list_off = 256;
-    L.list_cap = static_cast<size_t>(nnz) / (kWaveSortCap + 1) + 1;
-    L.global_off = align256(L.list_off + 4 * L.list_cap);
+    const size_t strips = height > 0 ? (static_cast<size_t>(rows) + height - 1) / height : 0;
+    L.small_off = 256;
+    L.small_cap = strips > 0 ? strips : 1;
+    L.big_off = align256(L.small_off + 4 * L.small_cap);
+    L.big_cap = static_cast<size_t>(nnz) / (kWaveSortCap + 1) + 1;
+    L.global_off = align256(L.big_off + 4 * L.big_cap);
     L.total = L.global_off + 16 * static_cast<size_t>(nnz);
     return L;
 }
@@ -368,23 +754,25 @@ hipError_t launch_from_csr(int32_t rows, int32_t cols, int32_t nnz, const int32_
                            hipStream_t stream) {
     (void)cols;
     const int strips = (rows + height - 1) / height;
-    const int g = (strips + 1 + 255) / 256;
-    hipLaunchKernelGGL(strip_ptr_kernel, dim3(g), dim3(256), 0, stream, strips, height, nnz, row_ptr, strip_ptr);
-    hipError_t e = hipGetLastError();
-    // No entries: the strip pointers are the whole result (and the sorted
-    // path's workspace is then zero bytes, so nothing may touch it).
-    if (e != hipSuccess || strips == 0 || nnz == 0) return e;
+    if (strips == 0) {
+        hipLaunchKernelGGL(set_ints_kernel, dim3(1), dim3(64), 0, stream, strip_ptr, 1, nnz);
+        return hipGetLastError();
+    }
+    const Conv cv{rows, strips, height, bits, nnz};
+    // No entries: nothing to pack or sort (and the sorted path's workspace is
+    // then zero bytes); the group kernel only writes the strip pointers.
+    if (nnz == 0) flags &= ~CMRS_SORT;
     switch (dtype_bytes(dtype)) {
-        case 8: return from_csr_typed<uint64_t>(rows, nnz, row_ptr, col_ind, val_in, height, bits, flags, col_word, val_out, workspace, stream);
-        case 4: return from_csr_typed<uint32_t>(rows, nnz, row_ptr, col_ind, val_in, height, bits, flags, col_word, val_out, workspace, stream);
-        default: return from_csr_typed<uint16_t>(rows, nnz, row_ptr, col_ind, val_in, height, bits, flags, col_word, val_out, workspace, stream);
+        case 8: return from_csr_typed<uint64_t>(cv, flags, row_ptr, col_ind, val_in, strip_ptr, col_word, val_out, workspace, stream);
+        case 4: return from_csr_typed<uint32_t>(cv, flags, row_ptr, col_ind, val_in, strip_ptr, col_word, val_out, workspace, stream);
+        default: return from_csr_typed<uint16_t>(cv, flags, row_ptr, col_ind, val_in, strip_ptr, col_word, val_out, workspace, stream);
     }
 }
 
 hipError_t launch_to_csr(const cmrs_mat_t* A, int32_t* row_ptr, int32_t* col_ind, void* val_out,
                          hipStream_t stream) {
     if (A->rows == 0) {
-        hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, stream, row_ptr, 0);
+        hipLaunchKernelGGL(set_ints_kernel, dim3(1), dim3(64), 0, stream, row_ptr, 1, 0);
         return hipGetLastError();
     }
     switch (dtype_bytes(A->val_dtype)) {
@@ -396,7 +784,7 @@ hipError_t launch_to_csr(const cmrs_mat_t* A, int32_t* row_ptr, int32_t* col_ind
 
 hipError_t launch_validate_csr(int32_t rows, int32_t cols, int32_t nnz, const int32_t* row_ptr,
                                const int32_t* col_ind, int32_t* flag, hipStream_t stream) {
-    hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, stream, flag, 0);
+    hipLaunchKernelGGL(set_ints_kernel, dim3(1), dim3(64), 0, stream, flag, 1, 0);
     int work = rows > nnz ? rows : nnz;
     int g = (work + 255) / 256;
     if (g < 1) g = 1;

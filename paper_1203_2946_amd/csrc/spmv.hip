@@ -205,35 +205,53 @@ __global__ __launch_bounds__(kSpmvThreads) void spmv_kernel(
     }
 }
 
-// Strip groups: one wave processes NG = 64/G strips at once, G lanes per
-// strip.  Lane q of group g walks entries lo+q, lo+q+G, ... of its strip with
-// U stream loads and then U gathers in flight, so a wave keeps 64*U entries
-// of memory traffic outstanding instead of one strip's.  Partials live in
-// LDS slot (g*HB + r)*G + q (each lane owns its slots, as in Algorithm 1).
-// Strips longer than long_len are skipped by their group and processed
-// afterwards by the whole wave, one at a time, with the per-lane layout of
-// spmv_kernel.  Requires G >= HB.
-template <int HB, int G, int U, bool NT, typename VT, typename XT, typename AT>
-__global__ __launch_bounds__(kSpmvThreads) void spmv_group_kernel(
-    int rows, int strips, int height, int bits, const int* __restrict__ strip_ptr,
-    const uint32_t* __restrict__ word, const VT* __restrict__ val, const XT* __restrict__ x, XT* __restrict__ y,
-    int long_len) {
-    static_assert(G >= HB && G <= kWave, "group width");
+// Sum each (group g, row r) set of G partials held in LDS slots
+// ((g*HB + r)*G + q, q < G) and hand the sum to out(g, r, sum).  There are
+// S = NG*HB sums: with S <= 64, L = 64/S lanes share one sum (xor butterfly);
+// otherwise every lane takes S/64 whole sums.  out() is called by a subset of
+// the lanes and must not use cross-lane operations.
+template <int HB, int G, typename AT, typename Out>
+__device__ inline void group_reduce(const AT* b, int lane, Out out) {
     constexpr int NG = kWave / G;
-    __shared__ AT buf[kSpmvWaves][HB * kWave];
-    const int lane = lane_id();
-    const int wave = uniform(static_cast<int>(threadIdx.x) / kWave);
-    const int strip0 = (xcd_logical_block(blockIdx.x, gridDim.x) * kSpmvWaves + wave) * NG;
-    if (strip0 >= strips) return;
-    const int g = lane / G, q = lane % G;
-    const int strip = strip0 + g;
-    int lo = 0, hi = 0;
-    if (strip < strips) {
-        lo = strip_ptr[strip];
-        hi = strip_ptr[strip + 1];
+    constexpr int S = NG * HB;
+    if constexpr (S <= kWave) {
+        constexpr int L = kWave / S;
+        constexpr int PER = G / L;
+        const int si = lane / L, part = lane % L;
+        const AT* pp = b + si * G + part * PER;
+        AT s = pp[0];
+#pragma unroll
+        for (int i = 1; i < PER; ++i) s += pp[i];
+#pragma unroll
+        for (int off = L / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+        if (part == 0) out(si / HB, si % HB, s);
+    } else {
+        constexpr int K = S / kWave;
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const int si = lane + kWave * i;
+            const AT* pp = b + si * G;
+            AT s = pp[0];
+#pragma unroll
+            for (int j = 1; j < G; ++j) s += pp[j];
+            out(si / HB, si % HB, s);
+        }
     }
+}
+
+// Strip groups: one wave processes NG = 64/G runs at once (a run is a strip,
+// or one column block of a strip), G lanes per run.  Lane q of group g walks
+// entries lo+q, lo+q+G, ... with U stream loads and then U gathers in flight,
+// so a wave keeps 64*U entries of memory traffic outstanding instead of one
+// strip's.  Partials live in LDS slot (g*HB + r)*G + q (each lane owns its
+// slots, as in Algorithm 1).  Runs longer than long_len are skipped by their
+// group and processed afterwards by the whole wave, one at a time, with the
+// per-lane layout of spmv_kernel.  out(g, r, sum) receives every row sum.
+template <int HB, int G, int U, bool NT, typename VT, typename XT, typename AT, typename Out>
+__device__ inline void group_runs(int lo, int hi, int long_len, int bits, const uint32_t* __restrict__ word,
+                                  const VT* __restrict__ val, const XT* __restrict__ x, AT* b, int lane, Out out) {
+    const int g = lane / G, q = lane % G;
     const bool is_long = hi - lo > long_len;
-    AT* b = buf[wave];
     const uint32_t mask = (1u << bits) - 1u;
 #pragma unroll
     for (int r = 0; r < HB; ++r) b[(g * HB + r) * G + q] = AT(0);
@@ -267,40 +285,94 @@ __global__ __launch_bounds__(kSpmvThreads) void spmv_group_kernel(
         }
     }
     wave_lds_sync();
-    {
-        // NG*HB sums of G partials; L = G/HB lanes per sum, HB partials each.
-        constexpr int L = G / HB;
-        const int si = lane / L, part = lane % L;
-        const AT* pp = b + si * G + part * HB;
-        AT s = pp[0];
-#pragma unroll
-        for (int i = 1; i < HB; ++i) s += pp[i];
-#pragma unroll
-        for (int off = L / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off);
-        const int gg = si / HB, rr = si % HB;
-        const bool grp_long = __shfl(static_cast<int>(is_long), gg * G) != 0;
-        const int st = strip0 + gg;
-        const int row = st * height + rr;
-        if (part == 0 && st < strips && !grp_long && rr < height && row < rows) y[row] = static_cast<XT>(s);
-    }
-    uint64_t longs = ballot(is_long && q == 0);
+    const uint64_t longs = ballot(is_long && q == 0);
+    group_reduce<HB, G, AT>(b, lane, [&](int gg, int rr, AT s) {
+        if (!((longs >> (gg * G)) & 1ull)) out(gg, rr, s);
+    });
     if (longs == 0) return;
     wave_lds_sync();
-    while (longs) {
-        const int leader = __ffsll(static_cast<unsigned long long>(longs)) - 1;
-        longs &= longs - 1;
+    uint64_t rest = longs;
+    while (rest) {
+        const int leader = __ffsll(static_cast<unsigned long long>(rest)) - 1;
+        rest &= rest - 1;
         const int llo = __shfl(lo, leader), lhi = __shfl(hi, leader);
-        const int st = strip0 + leader / G;
         LdsAcc<HB, AT> acc{b};
         acc.init(lane);
         accumulate_run<U, NT, VT, XT, AT>(acc, llo, lhi, bits, word, val, x, lane);
         const AT s = acc.finish(lane);
         constexpr int GW = kWave / HB;
-        const int r = lane / GW;
-        const int row = st * height + r;
-        if ((lane % GW) == 0 && r < height && row < rows) y[row] = static_cast<XT>(s);
+        if ((lane % GW) == 0) out(leader / G, lane / GW, s);
         wave_lds_sync();
     }
+}
+
+// Whole strips, y overwritten.
+template <int HB, int G, int U, bool NT, typename VT, typename XT, typename AT>
+__global__ __launch_bounds__(kSpmvThreads) void spmv_group_kernel(
+    int rows, int strips, int height, int bits, const int* __restrict__ strip_ptr,
+    const uint32_t* __restrict__ word, const VT* __restrict__ val, const XT* __restrict__ x, XT* __restrict__ y,
+    int long_len) {
+    constexpr int NG = kWave / G;
+    __shared__ AT buf[kSpmvWaves][HB * kWave];
+    const int lane = lane_id();
+    const int wave = uniform(static_cast<int>(threadIdx.x) / kWave);
+    const int strip0 = (xcd_logical_block(blockIdx.x, gridDim.x) * kSpmvWaves + wave) * NG;
+    if (strip0 >= strips) return;
+    const int strip = strip0 + lane / G;
+    int lo = 0, hi = 0;
+    if (strip < strips) {
+        lo = strip_ptr[strip];
+        hi = strip_ptr[strip + 1];
+    }
+    group_runs<HB, G, U, NT, VT, XT, AT>(lo, hi, long_len, bits, word, val, x, buf[wave], lane,
+                                         [&](int gg, int rr, AT s) {
+                                             const int st = strip0 + gg;
+                                             const int row = st * height + rr;
+                                             if (st < strips && rr < height && row < rows) y[row] = static_cast<XT>(s);
+                                         });
+}
+
+// Column-blocked schedule in one launch: workgroup b takes column block
+// b % nb (with nb = 8 that is the XCD the workgroup runs on, so each XCD
+// gathers from one eighth of x) and strips from (b / nb) onward; run cb of
+// each strip goes to partial[cb * rows + row].  colblock_combine_kernel then
+// adds the nb partials of every row in block order.
+template <int HB, int G, int U, bool NT, typename VT, typename XT, typename AT>
+__global__ __launch_bounds__(kSpmvThreads) void spmv_colblock_concurrent_kernel(
+    int rows, int strips, int height, int bits, const int* __restrict__ strip_ptr,
+    const uint32_t* __restrict__ word, const VT* __restrict__ val, const XT* __restrict__ x,
+    AT* __restrict__ partial, const int* __restrict__ split, int nb, int long_len) {
+    constexpr int NG = kWave / G;
+    __shared__ AT buf[kSpmvWaves][HB * kWave];
+    const int lane = lane_id();
+    const int wave = uniform(static_cast<int>(threadIdx.x) / kWave);
+    const int cb = static_cast<int>(blockIdx.x) % nb;
+    const int strip0 = (static_cast<int>(blockIdx.x) / nb * kSpmvWaves + wave) * NG;
+    if (strip0 >= strips) return;
+    const int strip = strip0 + lane / G;
+    int lo = 0, hi = 0;
+    if (strip < strips) {
+        const int* sp = split + static_cast<size_t>(strip) * (nb - 1);
+        lo = cb == 0 ? strip_ptr[strip] : sp[cb - 1];
+        hi = cb == nb - 1 ? strip_ptr[strip + 1] : sp[cb];
+    }
+    AT* part = partial + static_cast<size_t>(cb) * rows;
+    group_runs<HB, G, U, NT, VT, XT, AT>(lo, hi, long_len, bits, word, val, x, buf[wave], lane,
+                                         [&](int gg, int rr, AT s) {
+                                             const int st = strip0 + gg;
+                                             const int row = st * height + rr;
+                                             if (st < strips && rr < height && row < rows) part[row] = s;
+                                         });
+}
+
+template <typename XT, typename AT>
+__global__ __launch_bounds__(256) void colblock_combine_kernel(int rows, int nb, const AT* __restrict__ partial,
+                                                               XT* __restrict__ y) {
+    const int i = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= rows) return;
+    AT s = partial[i];
+    for (int k = 1; k < nb; ++k) s += partial[static_cast<size_t>(k) * rows + i];
+    y[i] = static_cast<XT>(s);
 }
 
 // Plan of the column-blocked schedule: split[s*(nb-1) + b-1] = first entry of
@@ -339,6 +411,7 @@ struct Launch {
     const int* split;
     int nb;
     hipStream_t stream;
+    void* partial = nullptr;  // concurrent column-blocked schedule: nb * rows partial sums
 };
 
 template <typename VT, typename XT, typename AT, int HB, bool NT, bool REG>
@@ -397,8 +470,41 @@ hipError_t launch_group(const Launch& L) {
     return launch_group_g<VT, XT, AT, HB, 64, NT>(L);
 }
 
+template <typename VT, typename XT, typename AT, int HB, int G>
+hipError_t launch_concurrent_g(const Launch& L) {
+    constexpr int NG = kWave / G;
+    constexpr int U = 8;
+    const int waves = (L.strips + NG - 1) / NG;
+    const int blocks_per_cb = (waves + kSpmvWaves - 1) / kSpmvWaves;
+    auto* part = static_cast<AT*>(L.partial);
+    hipLaunchKernelGGL((spmv_colblock_concurrent_kernel<HB, G, U, true, VT, XT, AT>), dim3(blocks_per_cb * L.nb),
+                       dim3(kSpmvThreads), 0, L.stream, L.A->rows, L.strips, L.A->height, L.A->bits, L.A->strip_ptr,
+                       L.A->col_word, static_cast<const VT*>(L.A->val), static_cast<const XT*>(L.x), part, L.split,
+                       L.nb, 4 * U * G);
+    hipLaunchKernelGGL((colblock_combine_kernel<XT, AT>), dim3((L.A->rows + 255) / 256), dim3(256), 0, L.stream,
+                       L.A->rows, L.nb, static_cast<const AT*>(part), static_cast<XT*>(L.y));
+    return hipGetLastError();
+}
+
+// Lanes per column-block run: about 8 entries per lane for the average run.
+template <typename VT, typename XT, typename AT, int HB>
+hipError_t launch_concurrent(const Launch& L) {
+    const double avg = static_cast<double>(L.A->nnz) / (static_cast<double>(L.strips) * L.nb);
+    int g = 2;
+    while (g < 64 && g * 8 * 1.5 < avg) g <<= 1;
+    switch (g) {
+        case 2: return launch_concurrent_g<VT, XT, AT, HB, 2>(L);
+        case 4: return launch_concurrent_g<VT, XT, AT, HB, 4>(L);
+        case 8: return launch_concurrent_g<VT, XT, AT, HB, 8>(L);
+        case 16: return launch_concurrent_g<VT, XT, AT, HB, 16>(L);
+        case 32: return launch_concurrent_g<VT, XT, AT, HB, 32>(L);
+        default: return launch_concurrent_g<VT, XT, AT, HB, 64>(L);
+    }
+}
+
 template <typename VT, typename XT, typename AT, int HB>
 hipError_t launch_hb(int variant, const Launch& L) {
+    if (L.partial != nullptr) return launch_concurrent<VT, XT, AT, HB>(L);
     if (variant == CMRS_SPMV_GROUP || variant == CMRS_SPMV_GROUP_NT) {
         if (L.split == nullptr)
             return variant == CMRS_SPMV_GROUP_NT ? launch_group<VT, XT, AT, HB, true>(L)
@@ -436,7 +542,7 @@ hipError_t dispatch(int variant, const Launch& L) {
 int resolve_spmv_variant(const cmrs_mat_t* A, int variant) {
     (void)A;
     if (variant != CMRS_SPMV_AUTO) return variant;
-    return CMRS_SPMV_LDS;
+    return CMRS_SPMV_GROUP_NT;
 }
 
 hipError_t launch_spmv(const cmrs_mat_t* A, const void* x, void* y, cmrs_dtype_t xy_dtype, int variant,
@@ -457,12 +563,14 @@ hipError_t launch_colblock_plan(const cmrs_mat_t* A, int nb, int bw, int* split,
 }
 
 hipError_t launch_spmv_colblock(const cmrs_mat_t* A, const void* x, void* y, int variant, int nb,
-                                const int* split, hipStream_t stream) {
+                                const int* split, int schedule, void* workspace, hipStream_t stream) {
     const int strips = (A->rows + A->height - 1) / A->height;
     if (strips == 0) return hipSuccess;
     variant = resolve_spmv_variant(A, variant);
     if (nb <= 1) return dispatch(variant, Launch{A, strips, x, y, nullptr, 1, stream});
-    return dispatch(variant, Launch{A, strips, x, y, split, nb, stream});
+    Launch L{A, strips, x, y, split, nb, stream};
+    if (schedule == CMRS_COLBLOCK_CONCURRENT) L.partial = workspace;
+    return dispatch(variant, L);
 }
 
 }  // namespace cmrs

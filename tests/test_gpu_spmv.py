@@ -239,12 +239,12 @@ def test_c3_full(C, c3, dtype):
             assert_low_bound(c3, hv, dtype, xs, x, y)
 
 
-def run_colblock(C, A, x64, height, nb, dtype="f64", variant="auto"):
+def run_colblock(C, A, x64, height, nb, dtype="f64", variant="auto", schedule="passes"):
     rp, ci, v, hv = G.upload(A, dtype)
     M = C.from_csr(rp, ci, v, A.cols, height, sort=True)
     plan = C.colblock_plan(M, nb)
     xt, xs64 = G.xy_vector(x64, dtype)
-    y = C.spmv_colblock(M, plan, xt, variant=variant)
+    y = C.spmv_colblock(M, plan, xt, variant=variant, schedule=schedule)
     torch.cuda.synchronize()
     return y.cpu().numpy().astype(np.float64), hv, xs64, M, plan
 
@@ -254,8 +254,8 @@ def run_colblock(C, A, x64, height, nb, dtype="f64", variant="auto"):
 def test_colblock(C, nb, height):
     A = synth.random_csr(3000, 2000, max_row=40, seed=nb + height, int_values=True)
     x = np.random.default_rng(nb).integers(-7, 8, A.cols).astype(np.float64)
-    for variant in ("lds", "reg", "group_nt"):
-        y, _, _, M, plan = run_colblock(C, A, x, height, nb, variant=variant)
+    for variant, schedule in (("lds", "passes"), ("reg", "passes"), ("group_nt", "passes"), ("auto", "concurrent")):
+        y, _, _, M, plan = run_colblock(C, A, x, height, nb, variant=variant, schedule=schedule)
         assert np.array_equal(y, oracle.csr_spmv(A.row_ptr, A.col_ind, A.val, x))
     if nb > 1:
         # plan: first entry of each strip at or beyond each block boundary
@@ -272,11 +272,33 @@ def test_colblock(C, nb, height):
 def test_colblock_bounds_fp64_fp32(C):
     A = synth.poisson_rows(300000, 16.0, seed=5)
     x = synth.normal_vector(A.cols, seed=6)
-    for nb in (2, 4):
-        y, _, _, _, _ = run_colblock(C, A, x, 8, nb)
+    for nb, schedule in ((2, "passes"), (4, "passes"), (8, "concurrent"), (3, "concurrent")):
+        y, _, _, _, _ = run_colblock(C, A, x, 8, nb, schedule=schedule)
         assert_fp64_bound(A, x, y)
-        y, hv, xs, _, _ = run_colblock(C, A, x, 8, nb, "f32")
+        y, hv, xs, _, _ = run_colblock(C, A, x, 8, nb, "f32", schedule=schedule)
         assert_low_bound(A, hv, "f32", xs, x, y)
+        y, hv, xs, _, _ = run_colblock(C, A, x, 8, nb, "bf16", schedule=schedule)
+        assert_low_bound(A, hv, "bf16", xs, x, y)
+
+
+@pytest.mark.parametrize("height", [1, 8, 32])
+def test_colblock_concurrent_long_rows_and_c2(C, c2, c2x, height):
+    """Concurrent schedule on the full n = 2^20 workload and on rows long
+    enough to take the whole-wave path inside a column block."""
+    y, _, _, _, _ = run_colblock(C, c2, c2x, height, 8, schedule="concurrent")
+    assert_fp64_bound(c2, c2x, y)
+    rng = np.random.default_rng(11)
+    k = rng.integers(0, 3, 3000)
+    k[[0, 5, 2999]] = [20000, 9000, 4000]
+    cols = 40000
+    cl = [np.sort(rng.choice(cols, size=int(kk), replace=False)) for kk in k]
+    rp = np.zeros(3001, np.int64)
+    np.cumsum(k, out=rp[1:])
+    A = synth.Csr(3000, cols, rp.astype(np.int32), np.concatenate(cl).astype(np.int32), rng.standard_normal(int(k.sum())))
+    x = synth.normal_vector(cols, seed=3)
+    for nb in (2, 8):
+        y, _, _, _, _ = run_colblock(C, A, x, height, nb, schedule="concurrent")
+        assert_fp64_bound(A, x, y)
 
 
 def test_colblock_needs_sorted(C):
