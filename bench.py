@@ -1,26 +1,27 @@
 """Benchmark of the CMRS hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--height H] [--dtype f64|f32]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--height H] [--schedule S] [--dtype f64|f32]
 
 Workload: square n = 2^20 matrix, row lengths max(1, Poisson(16)), distinct
 uniform columns, N(0,1) values and x (seeded, synthetic).  One step is one
-pass of the whole hot path over it: CSR -> CMRS with the in-strip reorder,
-y = A x, CMRS -> CSR, every buffer preallocated and resident in HBM.
+pass of the whole hot path over it: CSR -> CMRS with the in-strip reorder, the
+SpMV y = A x (for the column-blocked schedules including the plan that
+locates each strip's column-block runs), and CMRS -> CSR, with every buffer
+preallocated and resident in HBM.
 
-Before the timed steps the SpMV alone is characterised for every strip height
-1..32, fp64 and fp32, both kernel variants, with the paper's protocol (11 calls,
-the longest dropped, mean and std of the rest; Sec. 6.3), cold (L2 and MALL
-flushed by a 1 GiB write before each call) and warm (back to back).  Unless
---height is given, the timed steps use the height with the best cold fp64 SpMV
-time.
+Before the timed steps every strip height 1..32 and SpMV schedule is measured
+with the paper's protocol (11 calls, the longest dropped, mean and std of the
+rest; Sec. 6.3), cold (L2 and MALL flushed by a 1 GiB write before each call)
+and warm, for fp64 and fp32.  Unless --height / --schedule are given, the timed
+steps use the (height, schedule) with the shortest fp64 step.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -33,6 +34,12 @@ if ROOT not in sys.path:
 
 METRIC = "CMRS SpMV GB/s & % HBM roofline (FP64/FP32); learned-vs-exhaustive tune ratio"
 HBM_PEAK_GBS = 8000.0
+SCHEDULES = {
+    "group": ("auto", None),            # strip groups, non-temporal stream loads (library default)
+    "wave": ("lds", None),              # one wave per strip, LDS partials (Algorithm 1 as printed)
+    "colblock4": ("auto", 4),           # column-blocked, one launch, 4 blocks
+    "colblock8": ("auto", 8),           # column-blocked, one launch, 8 blocks (one per XCD)
+}
 
 
 def log(*a):
@@ -44,12 +51,37 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=5)
-    p.add_argument("--height", type=int, default=0, help="strip height for the timed steps (0: best from sweep)")
+    p.add_argument("--height", type=int, default=0, help="strip height of the timed steps (0: from the sweep)")
+    p.add_argument("--schedule", choices=list(SCHEDULES), default=None)
     p.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     p.add_argument("--no-sweep", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--rows", type=int, default=1 << 20)
     return p.parse_args()
+
+
+def kernel_source_hash() -> str:
+    d = os.path.join(ROOT, "paper_1203_2946_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel_tag: str):
+    """HBM bytes per dispatch of `kernel_tag` from the committed counter
+    summary (profiles/traffic.txt), or None if it was taken from other kernel
+    sources than the ones built now."""
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    if not os.path.exists(path):
+        return None
+    src = kernel_source_hash()
+    for line in open(path):
+        f = dict(kv.split("=", 1) for kv in line.split() if "=" in kv)
+        if f.get("tag") == kernel_tag and f.get("src") == src:
+            return int(f["fetch_bytes"]) + int(f["write_bytes"])
+    return None
 
 
 def main():
@@ -80,11 +112,11 @@ def main():
     rp = torch.from_numpy(A.row_ptr).to(dev)
     ci = torch.from_numpy(A.col_ind).to(dev)
     v64 = torch.from_numpy(A.val).to(dev)
-    v32 = v64.float()
+    v_d = {"f64": v64, "f32": v64.float()}
     x_d = {"f64": torch.from_numpy(x64).to(dev), "f32": torch.from_numpy(x64).to(dev).float()}
-    v_d = {"f64": v64, "f32": v32}
     flush_buf = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
+    sizes = {"f64": 8, "f32": 4}
 
     def flush():
         flush_buf.fill_(1)
@@ -105,79 +137,115 @@ def main():
             pairs.append((s, e))
         torch.cuda.synchronize()
         t = sorted(s.elapsed_time(e) for s, e in pairs)[:-1]
-        return float(np.mean(t)), float(np.std(t)), float(np.median(t))
+        return float(np.mean(t)), float(np.std(t))
 
-    sizes = {"f64": (8, 8, 8), "f32": (4, 4, 4)}
+    class Pipeline:
+        """Preallocated buffers of one (dtype, height, schedule) and its step."""
 
-    def spmv_bytes(M, dt):
-        s_v, s_x, s_y = sizes[dt]
-        return (model.beta_plus(M.nnz, M.rows, M.cols, M.strips, s_v, s_x, s_y),
-                model.beta_minus(M.nnz, M.rows, M.cols, M.strips, s_v, s_x, s_y))
+        def __init__(self, dt, h, sched):
+            self.dt, self.h, self.sched = dt, h, sched
+            self.variant, self.nb = SCHEDULES[sched]
+            self.v = v_d[dt]
+            self.x = x_d[dt]
+            self.M = cmrs.from_csr(rp, ci, self.v, A.cols, h, sort=True)
+            self.ws = torch.empty(max(1, cmrs.from_csr_workspace_bytes(A.rows, A.nnz, h, True)), dtype=torch.uint8,
+                                  device=dev)
+            self.y = torch.empty(A.rows, dtype=self.x.dtype, device=dev)
+            self.out = (torch.empty_like(rp), torch.empty_like(ci), torch.empty_like(self.v))
+            if self.nb:
+                self.plan = cmrs.colblock_plan(self.M, self.nb)
+                self.cws = torch.empty(max(1, cmrs.spmv_colblock_workspace_bytes(self.M, self.nb, "concurrent")),
+                                       dtype=torch.uint8, device=dev)
+
+        def convert(self):
+            cmrs.from_csr(rp, ci, self.v, A.cols, self.h, sort=True, workspace=self.ws, out=self.M)
+
+        def make_plan(self):
+            if self.nb:
+                d = self.M.desc()
+                st = cmrs.lib.cmrs_colblock_plan(cmrs.ctypes.byref(d), self.nb, self.plan.split.data_ptr(),
+                                                 self.plan.nbytes, stream.cuda_stream)
+                cmrs._check(st, "cmrs_colblock_plan")
+
+        def spmv(self):
+            if self.nb:
+                cmrs.spmv_colblock(self.M, self.plan, self.x, out=self.y, variant=self.variant,
+                                   schedule="concurrent", workspace=self.cws)
+            else:
+                cmrs.spmv(self.M, self.x, out=self.y, variant=self.variant)
+
+        def back(self):
+            cmrs.to_csr(self.M, out=self.out)
+
+        def bytes(self):
+            s_v = sizes[self.dt]
+            b_from = model.from_csr_bytes(A.nnz, A.rows, self.M.strips, s_v)
+            b_plan = (4 * A.nnz + 4 * (self.M.strips + 1) + 4 * self.M.strips * (self.nb - 1)) if self.nb else 0
+            bp = model.beta_plus(A.nnz, A.rows, A.cols, self.M.strips, s_v, s_v, s_v)
+            bm = model.beta_minus(A.nnz, A.rows, A.cols, self.M.strips, s_v, s_v, s_v)
+            b_to = model.to_csr_bytes(A.nnz, A.rows, self.M.strips, s_v)
+            return b_from, b_plan, bp, bm, b_to
 
     # ---------------------------------------------------------------- sweep
     sweep = []
     if not args.no_sweep:
         for dt in ("f64", "f32"):
             for h in (1, 2, 4, 8, 16, 32):
-                M = cmrs.from_csr(rp, ci, v_d[dt], A.cols, h, sort=True)
-                y = torch.empty(A.rows, dtype=x_d[dt].dtype, device=dev)
-                bp, bm = spmv_bytes(M, dt)
-                for var in ("lds", "reg"):
-                    if var == "reg" and h > 8:
-                        continue
-                    fn = lambda: cmrs.spmv(M, x_d[dt], out=y, variant=var)  # noqa: E731
-                    fn()
-                    cm, cs, cmed = protocol(fn, cold=True)
-                    wm, ws, _ = protocol(fn, cold=False)
-                    row = {"dtype": dt, "height": h, "variant": var, "cold_ms": round(cm, 5),
-                           "cold_std_ms": round(cs, 5), "warm_ms": round(wm, 5),
-                           "gbs_plus_cold": round(bp / cm / 1e6, 1), "eta_plus_cold": round(bp / cm / 1e6 / HBM_PEAK_GBS, 4),
-                           "gbs_minus_cold": round(bm / cm / 1e6, 1),
-                           "gflops_cold": round(model.flops(M.nnz, M.rows) / cm / 1e6, 1),
-                           "gbs_plus_warm": round(bp / wm / 1e6, 1)}
-                    sweep.append(row)
-                    log(f"sweep {dt} h={h:2d} {var}: cold {cm * 1e3:7.1f} us ({row['gbs_plus_cold']:7.1f} GB/s, "
-                        f"eta+ {row['eta_plus_cold']:.3f})  warm {wm * 1e3:7.1f} us")
-                del M, y
+                row_conv = None
+                for sched in SCHEDULES:
+                    P = Pipeline(dt, h, sched)
+                    b_from, b_plan, bp, bm, b_to = P.bytes()
+                    if row_conv is None:
+                        tf, _ = protocol(P.convert, cold=True)
+                        tt, _ = protocol(P.back, cold=True)
+                        row_conv = (tf, tt)
+                    tf, tt = row_conv
+                    tp = protocol(P.make_plan, cold=True)[0] if P.nb else 0.0
+                    P.spmv()
+                    cm, cs = protocol(P.spmv, cold=True)
+                    wm, _ = protocol(P.spmv, cold=False)
+                    r = {"dtype": dt, "height": h, "schedule": sched, "spmv_cold_ms": round(cm, 5),
+                         "spmv_cold_std_ms": round(cs, 5), "spmv_warm_ms": round(wm, 5),
+                         "gbs_plus_cold": round(bp / cm / 1e6, 1), "eta_plus_cold": round(bp / cm / 1e6 / HBM_PEAK_GBS, 4),
+                         "gbs_minus_cold": round(bm / cm / 1e6, 1),
+                         "gflops_cold": round(model.flops(A.nnz, A.rows) / cm / 1e6, 1),
+                         "from_csr_ms": round(tf, 5), "plan_ms": round(tp, 5), "to_csr_ms": round(tt, 5),
+                         "step_ms": round(tf + tp + cm + tt, 5)}
+                    sweep.append(r)
+                    log(f"sweep {dt} h={h:2d} {sched:9s}: spmv cold {cm * 1e3:7.1f} us ({r['gbs_plus_cold']:7.1f} GB/s, "
+                        f"eta+ {r['eta_plus_cold']:.3f}) warm {wm * 1e3:7.1f} us | step {r['step_ms'] * 1e3:7.1f} us")
+                    del P
 
     dt = args.dtype
-    if args.height:
-        h = args.height
-    elif sweep:
-        best = min((r for r in sweep if r["dtype"] == dt and r["variant"] == "lds"), key=lambda r: r["cold_ms"])
-        h = best["height"]
+    cand = [r for r in sweep if r["dtype"] == dt]
+    if args.height and args.schedule:
+        h, sched = args.height, args.schedule
+    elif cand:
+        pool = [r for r in cand if (not args.height or r["height"] == args.height)
+                and (not args.schedule or r["schedule"] == args.schedule)]
+        best = min(pool, key=lambda r: r["step_ms"])
+        h, sched = best["height"], best["schedule"]
     else:
-        h = 8
-    log(f"timed steps: dtype={dt} height={h}")
+        h, sched = args.height or 8, args.schedule or "group"
+    log(f"timed steps: dtype={dt} height={h} schedule={sched}")
 
     # ---------------------------------------------------------------- timed steps
-    vv = v_d[dt]
-    M = cmrs.from_csr(rp, ci, vv, A.cols, h, sort=True)
-    ws_bytes = cmrs.from_csr_workspace_bytes(A.rows, A.nnz, h, True)
-    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
-    y = torch.empty(A.rows, dtype=x_d[dt].dtype, device=dev)
-    rp2 = torch.empty_like(rp)
-    ci2 = torch.empty_like(ci)
-    v2 = torch.empty_like(vv)
-    xx = x_d[dt]
+    P = Pipeline(dt, h, sched)
+    names = ["from_csr_sorted", "colblock_plan", "spmv", "to_csr"] if P.nb else ["from_csr_sorted", "spmv", "to_csr"]
+    calls = [P.convert, P.make_plan, P.spmv, P.back] if P.nb else [P.convert, P.spmv, P.back]
 
     def step(evs=None):
+        for k, fn in enumerate(calls):
+            if evs is not None:
+                evs[k].record(stream)
+            fn()
         if evs is not None:
-            evs[0].record(stream)
-        cmrs.from_csr(rp, ci, vv, A.cols, h, sort=True, workspace=ws, out=M)
-        if evs is not None:
-            evs[1].record(stream)
-        cmrs.spmv(M, xx, out=y)
-        if evs is not None:
-            evs[2].record(stream)
-        cmrs.to_csr(M, out=(rp2, ci2, v2))
-        if evs is not None:
-            evs[3].record(stream)
+            evs[len(calls)].record(stream)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    all_evs = [[ev() for _ in range(4)] for _ in range(args.steps)]
+    all_evs = [[ev() for _ in range(len(calls) + 1)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for i in range(args.steps):
@@ -185,41 +253,47 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     ms_per_step = wall * 1e3 / args.steps
-    seg = np.array([[e[k].elapsed_time(e[k + 1]) for k in range(3)] for e in all_evs])
-    seg_ms = seg.mean(axis=0)
+    seg_ms = np.array([[e[k].elapsed_time(e[k + 1]) for k in range(len(calls))] for e in all_evs]).mean(axis=0)
 
-    s_v = sizes[dt][0]
-    b_from = model.from_csr_bytes(A.nnz, A.rows, M.strips, s_v)
-    b_spmv, b_spmv_minus = spmv_bytes(M, dt)
-    b_to = model.to_csr_bytes(A.nnz, A.rows, M.strips, s_v)
-    b_step = b_from + b_spmv + b_to
+    b_from, b_plan, b_spmv, b_spmv_minus, b_to = P.bytes()
+    algb = {"from_csr_sorted": b_from, "colblock_plan": b_plan, "spmv": b_spmv, "to_csr": b_to}
+    b_step = sum(algb[n] for n in names)
     value = b_step / (ms_per_step * 1e-3) / 1e9
-    kern = {
-        "from_csr_sorted": {"ms": round(float(seg_ms[0]), 5), "alg_bytes": b_from,
-                            "gbs": round(b_from / seg_ms[0] / 1e6, 1)},
-        "spmv": {"ms": round(float(seg_ms[1]), 5), "alg_bytes": b_spmv,
-                 "gbs": round(b_spmv / seg_ms[1] / 1e6, 1)},
-        "to_csr": {"ms": round(float(seg_ms[2]), 5), "alg_bytes": b_to, "gbs": round(b_to / seg_ms[2] / 1e6, 1)},
-    }
+    kern = {n: {"ms": round(float(seg_ms[k]), 5), "alg_bytes": algb[n],
+                "gbs": round(algb[n] / seg_ms[k] / 1e6, 1)} for k, n in enumerate(names)}
     dom_name = max(kern, key=lambda k: kern[k]["ms"])
     dom = kern[dom_name]
     ach = dom["alg_bytes"] / dom["ms"] / 1e6
-    roofline = {"bound": "hbm", "kernel": dom_name, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
-    log(f"step {ms_per_step * 1e3:.1f} us (events: from {seg_ms[0] * 1e3:.1f}, spmv {seg_ms[1] * 1e3:.1f}, "
-        f"to {seg_ms[2] * 1e3:.1f} us) -> {value:.1f} GB/s")
+    tag = f"{dom_name}:{dt}:h{h}:{sched}"
+    traffic = read_traffic(tag)
+    roofline = {"bound": "hbm", "kernel": dom_name, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic}
+    log(f"step {ms_per_step * 1e3:.1f} us (" + ", ".join(f"{n} {seg_ms[k] * 1e3:.1f}" for k, n in enumerate(names))
+        + f" us) -> {value:.1f} GB/s")
 
-    # SpMV alone at the chosen height (cold, paper protocol)
-    fn = lambda: cmrs.spmv(M, xx, out=y)  # noqa: E731
-    cm, cs, cmed = protocol(fn, cold=True)
-    wm, wsd, _ = protocol(fn, cold=False)
-    spmv = {"height": h, "dtype": dt, "cold_ms": round(cm, 5), "cold_std_ms": round(cs, 5), "warm_ms": round(wm, 5),
-            "beta_plus_bytes": b_spmv, "beta_minus_bytes": b_spmv_minus,
+    # SpMV alone at the chosen configuration, paper protocol
+    cm, cs = protocol(P.spmv, cold=True)
+    wm, _ = protocol(P.spmv, cold=False)
+    spmv = {"height": h, "schedule": sched, "dtype": dt, "cold_ms": round(cm, 5), "cold_std_ms": round(cs, 5),
+            "warm_ms": round(wm, 5), "beta_plus_bytes": b_spmv, "beta_minus_bytes": b_spmv_minus,
             "gbs_plus_cold": round(b_spmv / cm / 1e6, 1), "eta_plus_cold": round(b_spmv / cm / 1e6 / HBM_PEAK_GBS, 4),
             "gbs_minus_cold": round(b_spmv_minus / cm / 1e6, 1),
             "eta_minus_cold": round(b_spmv_minus / cm / 1e6 / HBM_PEAK_GBS, 4),
             "gflops_cold": round(model.flops(A.nnz, A.rows) / cm / 1e6, 1),
             "gbs_plus_warm": round(b_spmv / wm / 1e6, 1)}
+
+    # Achievable ceilings: read-only pass over the streams (Sec. 6.3) and the random-gather rate into x.
+    sink = torch.zeros(1, dtype=torch.float64, device=dev)
+    ts, _ = protocol(lambda: cmrs.calib_stream_read(P.M, h, sink), cold=True)
+    stream_bytes = (4 + sizes[dt]) * A.nnz
+    idx = torch.from_numpy(np.random.default_rng(2).integers(0, A.cols, A.nnz).astype(np.int32)).to(dev)
+    tg, _ = protocol(lambda: cmrs.calib_gather(idx, P.x, sink), cold=True)
+    ceiling = {"stream_read_gbs": round(stream_bytes / ts / 1e6, 1),
+               "stream_read_frac_of_peak": round(stream_bytes / ts / 1e6 / HBM_PEAK_GBS, 4),
+               "random_gathers_per_s": round(A.nnz / (tg * 1e-3), 1),
+               "random_gather_ms_for_nnz": round(tg, 5),
+               "spmv_eta_plus_vs_stream_ceiling": round(b_spmv / cm / 1e6 / (stream_bytes / ts / 1e6), 4)}
+    log(f"ceilings: stream {ceiling['stream_read_gbs']} GB/s, gathers {ceiling['random_gathers_per_s'] / 1e9:.1f} G/s")
 
     # ---------------------------------------------------------------- CPU oracle baseline
     cpu = None
@@ -241,9 +315,10 @@ def main():
         for _ in range(reps):
             cpu_step()
         tc = (time.perf_counter() - t1) / reps
-        cpu = {"value": round(b_step / tc / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-               "sample": f"the full workload matrix, one step (oracle CSR->CMRS sorted, CSR SpMV, CMRS->CSR) "
-                         f"timed {reps}x after one untimed pass; {tc:.2f} s per step",
+        b_cpu = b_from + b_spmv + b_to
+        cpu = {"value": round(b_cpu / tc / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"the full workload matrix, one step (oracle CSR->CMRS sorted, CSR SpMV, CMRS->CSR; "
+                         f"{b_cpu} algorithmic bytes) timed {reps}x after one untimed pass; {tc:.2f} s per step",
                "ms_per_step": round(tc * 1e3, 1)}
         log(f"cpu oracle: {tc:.2f} s/step -> {cpu['value']} GB/s")
 
@@ -253,8 +328,10 @@ def main():
         "vs_baseline": None, "dtype": dt, "data": "synthetic",
         "config": {"workload": f"poisson16 n={A.rows} (row lengths max(1,Poisson(16)), distinct uniform columns, "
                                f"N(0,1) values and x, seed 0)", "rows": A.rows, "nnz": A.nnz, "height": h,
-                   "sorted": True, "step": "from_csr(sorted) + spmv + to_csr", "alg_bytes_per_step": b_step},
-        "roofline": roofline, "cpu_baseline": cpu, "spmv": spmv, "kernels": kern, "sweep": sweep,
+                   "schedule": sched, "sorted": True,
+                   "step": " + ".join(names), "alg_bytes_per_step": b_step},
+        "roofline": roofline, "cpu_baseline": cpu, "spmv": spmv, "ceiling": ceiling, "kernels": kern,
+        "kernel_src": kernel_source_hash(), "sweep": sweep,
     }
     print(json.dumps(out), flush=True)
 

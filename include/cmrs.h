@@ -221,6 +221,28 @@ cmrs_status_t cmrs_spmv_colblock(const cmrs_mat_t *A, const void *x, void *y, cm
 cmrs_status_t cmrs_validate_csr(int32_t rows, int32_t cols, int32_t nnz, const int32_t *row_ptr,
                                 const int32_t *col_ind, int32_t *flag_out, hipStream_t stream);
 
+/*
+ * Measurement aids (not part of y = A x).
+ *
+ * cmrs_calib_stream_read: the read-only kernel of Sec. 6.3 — it reads the
+ * packed words (4*nnz bytes) and values (nnz values of `dtype`) of a CMRS
+ * matrix with 16-byte non-temporal loads, while every 256-thread workgroup
+ * reserves lds_words_per_lane * 256 values of LDS (the per-lane buffer of a
+ * strip of that height), so it runs at the SpMV's occupancy.  Both arrays must
+ * be 16-byte aligned; a tail shorter than 16 bytes is not read.
+ * lds_words_per_lane in [0, 32].
+ *
+ * cmrs_calib_gather: reads x[idx[i]] for i < n (n up to 2^31 - 1; every idx
+ * below the length of x) and sums them; the rate of random single-element
+ * reads.  x_dtype R64F or R32F.
+ *
+ * sink: one device double, never written for real data.
+ */
+cmrs_status_t cmrs_calib_stream_read(const uint32_t *col_word, const void *val, int32_t nnz, cmrs_dtype_t dtype,
+                                     int32_t lds_words_per_lane, double *sink, hipStream_t stream);
+cmrs_status_t cmrs_calib_gather(const uint32_t *idx, int64_t n, const void *x, cmrs_dtype_t x_dtype, double *sink,
+                                hipStream_t stream);
+
 /* Static string for a status code. */
 const char *cmrs_status_string(cmrs_status_t s);
 

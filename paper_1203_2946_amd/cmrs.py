@@ -67,6 +67,10 @@ lib.cmrs_colblock_plan.restype = ctypes.c_int
 lib.cmrs_spmv_colblock_workspace.argtypes, lib.cmrs_spmv_colblock_workspace.restype = [_DP, _i32, _i32], _sz
 lib.cmrs_spmv_colblock.argtypes = [_DP, _vp, _vp, ctypes.c_int, _i32, _i32, _vp, _sz, _i32, _vp, _sz, _vp]
 lib.cmrs_spmv_colblock.restype = ctypes.c_int
+lib.cmrs_calib_stream_read.argtypes = [_vp, _vp, _i32, ctypes.c_int, _i32, _vp, _vp]
+lib.cmrs_calib_stream_read.restype = ctypes.c_int
+lib.cmrs_calib_gather.argtypes = [_vp, ctypes.c_int64, _vp, ctypes.c_int, _vp, _vp]
+lib.cmrs_calib_gather.restype = ctypes.c_int
 lib.cmrs_validate_csr.argtypes = [_i32, _i32, _i32, _vp, _vp, _vp, _vp]
 lib.cmrs_validate_csr.restype = ctypes.c_int
 lib.cmrs_status_string.argtypes, lib.cmrs_status_string.restype = [ctypes.c_int], ctypes.c_char_p
@@ -75,7 +79,7 @@ lib.cmrs_last_error.argtypes, lib.cmrs_last_error.restype = [], ctypes.c_char_p
 EXPORTED = ["cmrs_abi_version", "cmrs_num_strips", "cmrs_bits_for_height", "cmrs_from_csr_workspace",
             "cmrs_from_csr", "cmrs_to_csr_workspace", "cmrs_to_csr", "cmrs_spmv", "cmrs_validate_csr",
             "cmrs_colblock_plan_bytes", "cmrs_colblock_plan", "cmrs_spmv_colblock_workspace", "cmrs_spmv_colblock",
-            "cmrs_status_string", "cmrs_last_error"]
+            "cmrs_calib_stream_read", "cmrs_calib_gather", "cmrs_status_string", "cmrs_last_error"]
 
 
 class CmrsError(RuntimeError):
@@ -290,3 +294,17 @@ def validate_csr(row_ptr: torch.Tensor, col_ind: torch.Tensor, cols: int, stream
                                flag.data_ptr(), _stream(stream))
     _check(st, "cmrs_validate_csr")
     return int(flag.item())
+
+
+def calib_stream_read(A: CmrsMatrix, lds_words_per_lane: int, sink: torch.Tensor, stream=None) -> None:
+    """Read-only pass over A's word and value streams (Sec. 6.3 calibration)."""
+    st = lib.cmrs_calib_stream_read(_ptr(A.col_word), _ptr(A.val), A.nnz, _DT[A.val.dtype], lds_words_per_lane,
+                                    sink.data_ptr(), _stream(stream))
+    _check(st, "cmrs_calib_stream_read")
+
+
+def calib_gather(idx: torch.Tensor, x: torch.Tensor, sink: torch.Tensor, stream=None) -> None:
+    """sum of x[idx[i]]: random single-element read rate."""
+    _dev(idx, "idx", torch.int32)
+    st = lib.cmrs_calib_gather(_ptr(idx), idx.numel(), _ptr(x), _DT[x.dtype], sink.data_ptr(), _stream(stream))
+    _check(st, "cmrs_calib_gather")

@@ -237,6 +237,27 @@ cmrs_status_t cmrs_validate_csr(int32_t rows, int32_t cols, int32_t nnz, const i
                     "cmrs_validate_csr");
 }
 
+cmrs_status_t cmrs_calib_stream_read(const uint32_t* col_word, const void* val, int32_t nnz, cmrs_dtype_t dtype,
+                                     int32_t lds_words_per_lane, double* sink, hipStream_t stream) {
+    g_last_error[0] = 0;
+    if (nnz < 0 || !valid_dtype(dtype) || lds_words_per_lane < 0 || lds_words_per_lane > 32 || !sink)
+        return fail(CMRS_ERR_INVALID_VALUE, "bad calibration arguments");
+    if (nnz > 0 && (!col_word || !val)) return fail(CMRS_ERR_INVALID_VALUE, "NULL array");
+    if ((reinterpret_cast<uintptr_t>(col_word) | reinterpret_cast<uintptr_t>(val)) & 15u)
+        return fail(CMRS_ERR_INVALID_VALUE, "arrays must be 16-byte aligned");
+    return from_hip(cmrs::launch_calib_stream(col_word, val, nnz, dtype, lds_words_per_lane, sink, stream),
+                    "cmrs_calib_stream_read");
+}
+
+cmrs_status_t cmrs_calib_gather(const uint32_t* idx, int64_t n, const void* x, cmrs_dtype_t x_dtype, double* sink,
+                                hipStream_t stream) {
+    g_last_error[0] = 0;
+    if (n < 0 || n > 0x7fffffff || (x_dtype != CMRS_R64F && x_dtype != CMRS_R32F) || !sink)
+        return fail(CMRS_ERR_INVALID_VALUE, "bad calibration arguments");
+    if (n > 0 && (!idx || !x)) return fail(CMRS_ERR_INVALID_VALUE, "NULL array");
+    return from_hip(cmrs::launch_calib_gather(idx, n, x, x_dtype, sink, stream), "cmrs_calib_gather");
+}
+
 const char* cmrs_status_string(cmrs_status_t s) {
     switch (s) {
         case CMRS_OK: return "CMRS_OK";

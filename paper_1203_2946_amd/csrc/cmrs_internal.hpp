@@ -71,6 +71,11 @@ hipError_t launch_colblock_plan(const cmrs_mat_t* A, int nb, int bw, int* split,
 hipError_t launch_spmv_colblock(const cmrs_mat_t* A, const void* x, void* y, int variant, int nb, const int* split,
                                 int schedule, void* workspace, hipStream_t stream);
 
+hipError_t launch_calib_stream(const void* word, const void* val, int32_t nnz, cmrs_dtype_t dtype,
+                               int32_t lds_words_per_lane, double* sink, hipStream_t stream);
+hipError_t launch_calib_gather(const uint32_t* idx, int64_t n, const void* x, cmrs_dtype_t dtype, double* sink,
+                               hipStream_t stream);
+
 hipError_t launch_validate_csr(int32_t rows, int32_t cols, int32_t nnz, const int32_t* row_ptr,
                                const int32_t* col_ind, int32_t* flag, hipStream_t stream);
 
