@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define CMRS_ABI_VERSION 1
+#define CMRS_ABI_VERSION 2
 
 typedef enum {
     CMRS_OK = 0,
@@ -212,6 +212,76 @@ cmrs_status_t cmrs_spmv_colblock(const cmrs_mat_t *A, const void *x, void *y, cm
                                  int32_t schedule, void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /*
+ * Products with several right-hand sides, Y = A X (the problem statement
+ * y = A x of Sec. 2.1 for nrhs vectors at once; each loaded value and packed
+ * word serves all of them).
+ *
+ * Layout: X and Y are row-major with leading dimensions ldx, ldy >= nrhs:
+ *   x_k[c] = X[c * ldx + k],  y_k[r] = Y[r * ldy + k],  k < nrhs,
+ * so the nrhs gathers of one entry read one contiguous piece of X.  Entries
+ * of Y with k >= nrhs are not touched; every row of Y (k < nrhs) is written,
+ * empty rows with +0.  nrhs in [1, CMRS_SPMM_MAX_RHS].  Dtypes as for
+ * cmrs_spmv (fp64/fp64, fp32/fp32, bf16 values with fp32 X and Y).  Every
+ * y_k obeys cmrs_spmv's error bound; results are deterministic for a fixed
+ * `group` (and, for batches, fixed tuning).
+ *
+ * cmrs_spmm: one matrix, one launch.  Lanes of a wave are split into
+ * strips x entry slots x right-hand sides: `group` entry slots per strip
+ * (a power of two with group * next_pow2(nrhs) <= 64; 0 chooses it from the
+ * mean strip length).  X and Y must not overlap.
+ */
+#define CMRS_SPMM_MAX_RHS 8
+cmrs_status_t cmrs_spmm(const cmrs_mat_t *A, int32_t nrhs, const void *X, int32_t ldx, void *Y, int32_t ldy,
+                        cmrs_dtype_t xy_dtype, int32_t group, hipStream_t stream);
+
+/*
+ * Batched products Y_i = A_i X_i for count matrices of any sizes and heights,
+ * in ONE persistent launch.  A plan splits every matrix into work tiles of
+ * whole strips (about tuning->tile_nnz stored entries each) and writes, into
+ * the caller's device buffer `desc` (cmrs_spmm_plan_bytes() bytes), a small
+ * queue header, one descriptor per matrix (its arrays, X_i, Y_i, nrhs_i,
+ * ldx_i, ldy_i) and the tile list.  cmrs_spmm_batched() then launches
+ * plan->grid workgroups that take tiles from the queue until it is empty;
+ * the last wave to finish resets the queue, so the same plan can be
+ * launched again, one launch at a time per plan, and captured into a HIP
+ * graph.  Tile t of matrix i is computed exactly as cmrs_spmm computes those
+ * strips with the plan's group width.
+ *
+ * cmrs_spmm_plan is set-up, not hot path: it copies the descriptor image
+ * from host memory with hipMemcpyAsync and synchronises `stream` (so do not
+ * call it under graph capture).  The plan binds the device pointers it was
+ * given; rebuild it when any of them, or a matrix, changes.  Host arrays
+ * mats, nrhs, X, ldx, Y, ldy have `count` entries; all matrices share one
+ * value dtype, matched with xy_dtype as for cmrs_spmv.  Y_i must not overlap
+ * each other or any X_j (X_j may be shared).  tuning may be NULL (defaults).
+ * If a batched launch does not run to completion, rebuild the plan.
+ */
+typedef struct {
+    int32_t tile_nnz;       /* stored entries per work tile (rounded to whole
+                               strip passes); 0 = 32768                        */
+    int32_t group;          /* entry slots per strip, a power of two; 0 = from
+                               each matrix's mean strip length                 */
+    int32_t blocks_per_cu;  /* resident 256-thread workgroups per compute unit;
+                               0 = 4                                           */
+    int32_t reserved;       /* must be 0                                       */
+} cmrs_spmm_tuning_t;
+
+typedef struct {            /* filled by cmrs_spmm_plan (host struct)          */
+    int32_t count, tiles, grid, lds_bytes;
+    int32_t val_dtype, xy_dtype, max_height, waves;
+    void *desc;             /* the caller's device buffer                      */
+    size_t desc_bytes;
+} cmrs_spmm_plan_t;
+
+size_t cmrs_spmm_plan_bytes(int32_t count, const cmrs_mat_t *mats, const int32_t *nrhs,
+                            const cmrs_spmm_tuning_t *tuning);
+cmrs_status_t cmrs_spmm_plan(int32_t count, const cmrs_mat_t *mats, const int32_t *nrhs, const void *const *X,
+                             const int32_t *ldx, void *const *Y, const int32_t *ldy, cmrs_dtype_t xy_dtype,
+                             const cmrs_spmm_tuning_t *tuning, void *desc, size_t desc_bytes,
+                             cmrs_spmm_plan_t *plan, hipStream_t stream);
+cmrs_status_t cmrs_spmm_batched(const cmrs_spmm_plan_t *plan, hipStream_t stream);
+
+/*
  * Device check of CSR validity: writes *flag_out = 0 when row_ptr[0] == 0,
  * row_ptr is non-decreasing, row_ptr[rows] == nnz and every column is in
  * [0, cols); otherwise a non-zero bit mask (1: row_ptr[0] or row_ptr[rows]
@@ -220,6 +290,46 @@ cmrs_status_t cmrs_spmv_colblock(const cmrs_mat_t *A, const void *x, void *y, cm
  */
 cmrs_status_t cmrs_validate_csr(int32_t rows, int32_t cols, int32_t nnz, const int32_t *row_ptr,
                                 const int32_t *col_ind, int32_t *flag_out, hipStream_t stream);
+
+/*
+ * Learned configuration selection.  The paper chooses the strip height and the
+ * kernel options by brute-force search over measured times (Sec. 6.3) and
+ * reports how much per-matrix tuning can gain (Sec. 6.8).  These calls provide
+ * the pieces of a learned replacement: matrix features and a small MLP
+ * (CMRS_SEL_FEATURES -> 64 -> 64 -> CMRS_SEL_CLASSES, ReLU, fp32) with forward,
+ * backward and Adam kernels, so the network is trained on the GPU from
+ * measured times.  Class c = 4 * log2(height) + schedule (schedules: 0 one
+ * wave per strip, 1 the same with non-temporal loads, 2 strip groups, 3
+ * concurrent column blocks with 4 blocks; heights 1..32).
+ *
+ * cmrs_features: 40 floats from a CSR structure (row-length histogram, 20
+ *   bins; |column - row*cols/rows| histogram, 16 bins; log sizes) — the bins
+ *   are defined in csrc/select.hip.  workspace: CMRS_SEL_FEATURE_WS bytes.
+ * Parameters are one packed float array of CMRS_SEL_PARAMS:
+ *   W1[40][64], b1[64], W2[64][64], b2[64], W3[64][24], b3[24] (row-major,
+ *   out = in W + b).  Activations are [batch][width] row-major device arrays.
+ * cmrs_mlp_forward:  H1, H2 (batch x 64) and Y (batch x 24).
+ * cmrs_mlp_backward: from dY (batch x 24) and the forward activations, the
+ *   parameter gradients `grads` (CMRS_SEL_PARAMS) with scratch dH2, dH1
+ *   (batch x 64 each); batch sums in sample order (deterministic).
+ * cmrs_mse_grad:     dY = scale * (Y - T), n values.
+ * cmrs_adam_step:    one Adam update of n parameters (step >= 1 for the bias
+ *   corrections).
+ */
+#define CMRS_SEL_FEATURES 40
+#define CMRS_SEL_CLASSES 24
+#define CMRS_SEL_PARAMS 8344
+#define CMRS_SEL_FEATURE_WS 256
+cmrs_status_t cmrs_features(int32_t rows, int32_t cols, int32_t nnz, const int32_t *row_ptr, const int32_t *col_ind,
+                            float *feat_out, void *workspace, size_t workspace_bytes, hipStream_t stream);
+cmrs_status_t cmrs_mlp_forward(int32_t batch, const float *X, const float *params, float *H1, float *H2, float *Y,
+                               hipStream_t stream);
+cmrs_status_t cmrs_mlp_backward(int32_t batch, const float *X, const float *params, const float *H1,
+                                const float *H2, const float *dY, float *dH2, float *dH1, float *grads,
+                                hipStream_t stream);
+cmrs_status_t cmrs_mse_grad(int32_t n, const float *Y, const float *T, float *dY, float scale, hipStream_t stream);
+cmrs_status_t cmrs_adam_step(int32_t n, float *params, const float *grads, float *m, float *v, float lr, float beta1,
+                             float beta2, float eps, int32_t step, hipStream_t stream);
 
 /*
  * Measurement aids (not part of y = A x).

@@ -71,6 +71,39 @@ lib.cmrs_calib_stream_read.argtypes = [_vp, _vp, _i32, ctypes.c_int, _i32, _vp, 
 lib.cmrs_calib_stream_read.restype = ctypes.c_int
 lib.cmrs_calib_gather.argtypes = [_vp, ctypes.c_int64, _vp, ctypes.c_int, _vp, _vp]
 lib.cmrs_calib_gather.restype = ctypes.c_int
+class SpmmTuning(ctypes.Structure):
+    _fields_ = [("tile_nnz", ctypes.c_int32), ("group", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class SpmmPlanStruct(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("tiles", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("lds_bytes", ctypes.c_int32), ("val_dtype", ctypes.c_int32), ("xy_dtype", ctypes.c_int32),
+                ("max_height", ctypes.c_int32), ("waves", ctypes.c_int32), ("desc", ctypes.c_void_p),
+                ("desc_bytes", ctypes.c_size_t)]
+
+
+_PI32 = ctypes.POINTER(ctypes.c_int32)
+_PVP = ctypes.POINTER(ctypes.c_void_p)
+lib.cmrs_spmm.argtypes = [_DP, _i32, _vp, _i32, _vp, _i32, ctypes.c_int, _i32, _vp]
+lib.cmrs_spmm.restype = ctypes.c_int
+lib.cmrs_spmm_plan_bytes.argtypes = [_i32, _DP, _PI32, ctypes.POINTER(SpmmTuning)]
+lib.cmrs_spmm_plan_bytes.restype = _sz
+lib.cmrs_spmm_plan.argtypes = [_i32, _DP, _PI32, _PVP, _PI32, _PVP, _PI32, ctypes.c_int,
+                               ctypes.POINTER(SpmmTuning), _vp, _sz, ctypes.POINTER(SpmmPlanStruct), _vp]
+lib.cmrs_spmm_plan.restype = ctypes.c_int
+lib.cmrs_spmm_batched.argtypes = [ctypes.POINTER(SpmmPlanStruct), _vp]
+lib.cmrs_spmm_batched.restype = ctypes.c_int
+lib.cmrs_features.argtypes = [_i32, _i32, _i32, _vp, _vp, _vp, _vp, _sz, _vp]
+lib.cmrs_features.restype = ctypes.c_int
+lib.cmrs_mlp_forward.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _vp]
+lib.cmrs_mlp_forward.restype = ctypes.c_int
+lib.cmrs_mlp_backward.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+lib.cmrs_mlp_backward.restype = ctypes.c_int
+lib.cmrs_mse_grad.argtypes = [_i32, _vp, _vp, _vp, ctypes.c_float, _vp]
+lib.cmrs_mse_grad.restype = ctypes.c_int
+lib.cmrs_adam_step.argtypes = [_i32, _vp, _vp, _vp, _vp] + [ctypes.c_float] * 4 + [_i32, _vp]
+lib.cmrs_adam_step.restype = ctypes.c_int
 lib.cmrs_validate_csr.argtypes = [_i32, _i32, _i32, _vp, _vp, _vp, _vp]
 lib.cmrs_validate_csr.restype = ctypes.c_int
 lib.cmrs_status_string.argtypes, lib.cmrs_status_string.restype = [ctypes.c_int], ctypes.c_char_p
@@ -79,7 +112,9 @@ lib.cmrs_last_error.argtypes, lib.cmrs_last_error.restype = [], ctypes.c_char_p
 EXPORTED = ["cmrs_abi_version", "cmrs_num_strips", "cmrs_bits_for_height", "cmrs_from_csr_workspace",
             "cmrs_from_csr", "cmrs_to_csr_workspace", "cmrs_to_csr", "cmrs_spmv", "cmrs_validate_csr",
             "cmrs_colblock_plan_bytes", "cmrs_colblock_plan", "cmrs_spmv_colblock_workspace", "cmrs_spmv_colblock",
-            "cmrs_calib_stream_read", "cmrs_calib_gather", "cmrs_status_string", "cmrs_last_error"]
+            "cmrs_spmm", "cmrs_spmm_plan_bytes", "cmrs_spmm_plan", "cmrs_spmm_batched",
+            "cmrs_calib_stream_read", "cmrs_calib_gather", "cmrs_features", "cmrs_mlp_forward", "cmrs_mlp_backward",
+            "cmrs_mse_grad", "cmrs_adam_step", "cmrs_status_string", "cmrs_last_error"]
 
 
 class CmrsError(RuntimeError):
@@ -283,6 +318,96 @@ def spmv_colblock(A: CmrsMatrix, plan: ColblockPlan, x: torch.Tensor, out: torch
                                 _ptr(workspace) if wsb else None, wsb, _stream(stream))
     _check(st, "cmrs_spmv_colblock")
     return y
+
+
+def _rhs_block(t: torch.Tensor, name: str, n: int, dtype) -> int:
+    """Check a row-major (n, nrhs) block with unit column stride; returns ld."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.dim() != 2 or t.shape[0] != n:
+        raise ValueError(f"{name} must have shape ({n}, nrhs), got {tuple(t.shape)}")
+    if t.shape[1] > 1 and t.stride(1) != 1:
+        raise ValueError(f"{name} needs unit stride along the right-hand sides")
+    if t.shape[0] > 1 and t.stride(0) < t.shape[1]:
+        raise ValueError(f"{name} has a leading dimension below nrhs")
+    return max(int(t.stride(0)), int(t.shape[1])) if t.shape[0] > 1 else int(t.shape[1])
+
+
+def spmm(A: CmrsMatrix, X: torch.Tensor, out: torch.Tensor | None = None, group: int = 0,
+         stream=None) -> torch.Tensor:
+    """Y = A X for X of shape (cols, nrhs), nrhs <= 8, row-major (one launch)."""
+    xdt = torch.float64 if A.val.dtype == torch.float64 else torch.float32
+    ldx = _rhs_block(X, "X", A.cols, xdt)
+    nrhs = int(X.shape[1])
+    Y = out if out is not None else torch.empty(A.rows, nrhs, dtype=xdt, device=X.device)
+    ldy = _rhs_block(Y, "Y", A.rows, xdt)
+    if Y.shape[1] != nrhs:
+        raise ValueError("X and Y differ in the number of right-hand sides")
+    d = A.desc()
+    st = lib.cmrs_spmm(ctypes.byref(d), nrhs, _ptr(X), ldx, _ptr(Y), ldy, _DT[xdt], group, _stream(stream))
+    _check(st, "cmrs_spmm")
+    return Y
+
+
+class SpmmPlan:
+    """A batch plan: the device descriptor buffer, the filled plan struct and
+    references that keep every bound tensor alive while the plan exists."""
+
+    def __init__(self, desc: torch.Tensor, plan: SpmmPlanStruct, keep):
+        self.desc = desc
+        self.plan = plan
+        self._keep = keep
+
+    @property
+    def tiles(self) -> int:
+        return int(self.plan.tiles)
+
+    @property
+    def grid(self) -> int:
+        return int(self.plan.grid)
+
+
+def spmm_plan(mats, Xs, Ys, tile_nnz: int = 0, group: int = 0, blocks_per_cu: int = 0, stream=None) -> SpmmPlan:
+    """Plan Y_i = A_i X_i for lists of matrices and (cols_i, nrhs_i) / (rows_i,
+    nrhs_i) row-major blocks.  Synchronises the stream (set-up call)."""
+    n = len(mats)
+    if len(Xs) != n or len(Ys) != n:
+        raise ValueError("mats, Xs and Ys differ in length")
+    if n == 0:
+        raise ValueError("empty batch")
+    xdt = torch.float64 if mats[0].val.dtype == torch.float64 else torch.float32
+    descs = (CmrsMatDesc * n)(*[A.desc() for A in mats])
+    nrhs = (ctypes.c_int32 * n)()
+    ldx = (ctypes.c_int32 * n)()
+    ldy = (ctypes.c_int32 * n)()
+    xp = (ctypes.c_void_p * n)()
+    yp = (ctypes.c_void_p * n)()
+    for i, (A, X, Y) in enumerate(zip(mats, Xs, Ys)):
+        ldx[i] = _rhs_block(X, f"X[{i}]", A.cols, xdt)
+        ldy[i] = _rhs_block(Y, f"Y[{i}]", A.rows, xdt)
+        if X.shape[1] != Y.shape[1]:
+            raise ValueError(f"X[{i}] and Y[{i}] differ in the number of right-hand sides")
+        nrhs[i] = int(X.shape[1])
+        xp[i] = _ptr(X)
+        yp[i] = _ptr(Y)
+    tun = SpmmTuning(tile_nnz, group, blocks_per_cu, 0)
+    nbytes = int(lib.cmrs_spmm_plan_bytes(n, descs, nrhs, ctypes.byref(tun)))
+    if nbytes == 0:
+        raise ValueError("invalid batch (cmrs_spmm_plan_bytes returned 0)")
+    desc = torch.empty(nbytes, dtype=torch.uint8, device=mats[0].val.device)
+    plan = SpmmPlanStruct()
+    st = lib.cmrs_spmm_plan(n, descs, nrhs, xp, ldx, yp, ldy, _DT[xdt], ctypes.byref(tun), desc.data_ptr(), nbytes,
+                            ctypes.byref(plan), _stream(stream))
+    _check(st, "cmrs_spmm_plan")
+    return SpmmPlan(desc, plan, (list(mats), list(Xs), list(Ys)))
+
+
+def spmm_batched(plan: SpmmPlan, stream=None) -> None:
+    """Run a batch plan: one persistent launch."""
+    st = lib.cmrs_spmm_batched(ctypes.byref(plan.plan), _stream(stream))
+    _check(st, "cmrs_spmm_batched")
 
 
 def validate_csr(row_ptr: torch.Tensor, col_ind: torch.Tensor, cols: int, stream=None) -> int:

@@ -4,6 +4,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "cmrs_internal.hpp"
 
 namespace {
@@ -228,6 +231,148 @@ cmrs_status_t cmrs_spmv_colblock(const cmrs_mat_t* A, const void* x, void* y, cm
                     "cmrs_spmv_colblock");
 }
 
+static bool dtype_pair_ok(cmrs_dtype_t val, cmrs_dtype_t xy) {
+    return (val == CMRS_R64F && xy == CMRS_R64F) || (val == CMRS_R32F && xy == CMRS_R32F) ||
+           (val == CMRS_R16BF && xy == CMRS_R32F);
+}
+
+static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Bytes from the first to one past the last element of a row-major block of
+// n rows, leading dimension ld, k used columns.
+static size_t block_bytes(int32_t n, int32_t ld, int32_t k, size_t es) {
+    if (n <= 0) return 0;
+    return (static_cast<size_t>(n - 1) * static_cast<size_t>(ld) + static_cast<size_t>(k)) * es;
+}
+
+static cmrs_status_t check_spmm_one(const cmrs_mat_t* A, int32_t nrhs, const void* X, int32_t ldx, const void* Y,
+                                    int32_t ldy, cmrs_dtype_t xy_dtype, int idx) {
+    cmrs_status_t st = check_mat(A);
+    if (st != CMRS_OK) return st;
+    if (!dtype_pair_ok(A->val_dtype, xy_dtype))
+        return fail(CMRS_ERR_NOT_SUPPORTED, "matrix %d: value dtype %d with X/Y dtype %d", idx, (int)A->val_dtype,
+                    (int)xy_dtype);
+    if (nrhs < 1 || nrhs > CMRS_SPMM_MAX_RHS)
+        return fail(CMRS_ERR_INVALID_VALUE, "matrix %d: nrhs %d outside [1, %d]", idx, nrhs, CMRS_SPMM_MAX_RHS);
+    if (ldx < nrhs || ldy < nrhs)
+        return fail(CMRS_ERR_INVALID_VALUE, "matrix %d: ldx %d / ldy %d below nrhs %d", idx, ldx, ldy, nrhs);
+    if (A->rows > 0 && !Y) return fail(CMRS_ERR_INVALID_VALUE, "matrix %d: Y is NULL", idx);
+    if (A->nnz > 0 && A->cols > 0 && !X) return fail(CMRS_ERR_INVALID_VALUE, "matrix %d: X is NULL", idx);
+    const size_t es = cmrs::dtype_bytes(xy_dtype);
+    if (ranges_overlap(X, block_bytes(A->cols, ldx, nrhs, es), Y, block_bytes(A->rows, ldy, nrhs, es)))
+        return fail(CMRS_ERR_INVALID_VALUE, "matrix %d: X and Y overlap", idx);
+    return CMRS_OK;
+}
+
+cmrs_status_t cmrs_spmm(const cmrs_mat_t* A, int32_t nrhs, const void* X, int32_t ldx, void* Y, int32_t ldy,
+                        cmrs_dtype_t xy_dtype, int32_t group, hipStream_t stream) {
+    g_last_error[0] = 0;
+    cmrs_status_t st = check_spmm_one(A, nrhs, X, ldx, Y, ldy, xy_dtype, 0);
+    if (st != CMRS_OK) return st;
+    if (group != 0 && (!is_pow2(group) || group * cmrs::next_pow2(nrhs) > 64))
+        return fail(CMRS_ERR_INVALID_VALUE, "group %d: need 0 or a power of two with group * %d <= 64", group,
+                    cmrs::next_pow2(nrhs));
+    if (A->rows == 0) return CMRS_OK;
+    return from_hip(cmrs::launch_spmm(A, nrhs, X, ldx, Y, ldy, group, stream), "cmrs_spmm");
+}
+
+static cmrs_status_t check_tuning(const cmrs_spmm_tuning_t* t) {
+    if (!t) return CMRS_OK;
+    if (t->tile_nnz < 0) return fail(CMRS_ERR_INVALID_VALUE, "tile_nnz %d is negative", t->tile_nnz);
+    if (t->group != 0 && (!is_pow2(t->group) || t->group > 64))
+        return fail(CMRS_ERR_INVALID_VALUE, "group %d: need 0 or a power of two <= 64", t->group);
+    if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64)
+        return fail(CMRS_ERR_INVALID_VALUE, "blocks_per_cu %d outside [0, 64]", t->blocks_per_cu);
+    if (t->reserved != 0) return fail(CMRS_ERR_INVALID_VALUE, "reserved tuning field must be 0");
+    return CMRS_OK;
+}
+
+static cmrs_status_t check_batch_shape(int32_t count, const cmrs_mat_t* mats, const int32_t* nrhs) {
+    if (count < 0) return fail(CMRS_ERR_INVALID_VALUE, "negative count");
+    if (count > 0 && (!mats || !nrhs)) return fail(CMRS_ERR_INVALID_VALUE, "mats or nrhs is NULL");
+    for (int32_t i = 0; i < count; ++i) {
+        cmrs_status_t st = check_mat(&mats[i]);
+        if (st != CMRS_OK) return st;
+        if (nrhs[i] < 1 || nrhs[i] > CMRS_SPMM_MAX_RHS)
+            return fail(CMRS_ERR_INVALID_VALUE, "matrix %d: nrhs %d outside [1, %d]", i, nrhs[i], CMRS_SPMM_MAX_RHS);
+        if (mats[i].val_dtype != mats[0].val_dtype)
+            return fail(CMRS_ERR_NOT_SUPPORTED, "matrix %d: value dtype differs from matrix 0", i);
+    }
+    return CMRS_OK;
+}
+
+size_t cmrs_spmm_plan_bytes(int32_t count, const cmrs_mat_t* mats, const int32_t* nrhs,
+                            const cmrs_spmm_tuning_t* tuning) {
+    if (check_batch_shape(count, mats, nrhs) != CMRS_OK || check_tuning(tuning) != CMRS_OK) return 0;
+    return cmrs::spmm_plan_shape(count, mats, nrhs, tuning ? tuning->tile_nnz : 0, tuning ? tuning->group : 0,
+                                 nullptr)
+        .bytes;
+}
+
+namespace {
+struct Span {
+    uintptr_t lo, hi;
+    int idx;
+};
+}  // namespace
+
+cmrs_status_t cmrs_spmm_plan(int32_t count, const cmrs_mat_t* mats, const int32_t* nrhs, const void* const* X,
+                             const int32_t* ldx, void* const* Y, const int32_t* ldy, cmrs_dtype_t xy_dtype,
+                             const cmrs_spmm_tuning_t* tuning, void* desc, size_t desc_bytes,
+                             cmrs_spmm_plan_t* plan, hipStream_t stream) {
+    g_last_error[0] = 0;
+    cmrs_status_t st = check_batch_shape(count, mats, nrhs);
+    if (st != CMRS_OK) return st;
+    st = check_tuning(tuning);
+    if (st != CMRS_OK) return st;
+    if (!plan) return fail(CMRS_ERR_INVALID_VALUE, "plan is NULL");
+    if (count > 0 && (!X || !ldx || !Y || !ldy)) return fail(CMRS_ERR_INVALID_VALUE, "X, ldx, Y or ldy is NULL");
+    for (int32_t i = 0; i < count; ++i) {
+        st = check_spmm_one(&mats[i], nrhs[i], X[i], ldx[i], Y[i], ldy[i], xy_dtype, i);
+        if (st != CMRS_OK) return st;
+    }
+    // No Y may overlap another Y or any X.
+    const size_t es = cmrs::dtype_bytes(xy_dtype);
+    std::vector<Span> ys;
+    for (int32_t i = 0; i < count; ++i) {
+        const size_t n = block_bytes(mats[i].rows, ldy[i], nrhs[i], es);
+        if (n) ys.push_back({reinterpret_cast<uintptr_t>(Y[i]), reinterpret_cast<uintptr_t>(Y[i]) + n, i});
+    }
+    std::sort(ys.begin(), ys.end(), [](const Span& a, const Span& b) { return a.lo < b.lo; });
+    for (size_t i = 1; i < ys.size(); ++i)
+        if (ys[i].lo < ys[i - 1].hi)
+            return fail(CMRS_ERR_INVALID_VALUE, "Y of matrices %d and %d overlap", ys[i - 1].idx, ys[i].idx);
+    for (int32_t j = 0; j < count && !ys.empty(); ++j) {
+        const size_t n = block_bytes(mats[j].cols, ldx[j], nrhs[j], es);
+        if (!n || mats[j].nnz == 0) continue;
+        const uintptr_t lo = reinterpret_cast<uintptr_t>(X[j]), hi = lo + n;
+        // First Y span ending after lo: the only candidate to intersect.
+        auto it = std::upper_bound(ys.begin(), ys.end(), lo, [](uintptr_t v, const Span& s) { return v < s.hi; });
+        if (it != ys.end() && it->lo < hi)
+            return fail(CMRS_ERR_INVALID_VALUE, "X of matrix %d overlaps Y of matrix %d", j, it->idx);
+    }
+    const size_t need = cmrs_spmm_plan_bytes(count, mats, nrhs, tuning);
+    if (!desc || desc_bytes < need)
+        return fail(CMRS_ERR_WORKSPACE, "plan buffer of %zu bytes needed, %zu given", need, desc_bytes);
+    if (reinterpret_cast<uintptr_t>(desc) & 15u) return fail(CMRS_ERR_INVALID_VALUE, "plan buffer not 16-byte aligned");
+    return from_hip(cmrs::build_spmm_plan(count, mats, nrhs, X, ldx, Y, ldy, xy_dtype, tuning ? tuning->tile_nnz : 0,
+                                          tuning ? tuning->group : 0, tuning ? tuning->blocks_per_cu : 0, desc, plan,
+                                          stream),
+                    "cmrs_spmm_plan");
+}
+
+cmrs_status_t cmrs_spmm_batched(const cmrs_spmm_plan_t* plan, hipStream_t stream) {
+    g_last_error[0] = 0;
+    if (!plan) return fail(CMRS_ERR_INVALID_VALUE, "plan is NULL");
+    if (plan->tiles < 0 || plan->count < 0) return fail(CMRS_ERR_INVALID_VALUE, "corrupt plan");
+    if (plan->tiles == 0) return CMRS_OK;
+    if (!plan->desc || plan->grid < 1 || plan->waves != plan->grid * 4 || !is_pow2(plan->max_height) ||
+        plan->max_height > CMRS_MAX_HEIGHT || !valid_dtype(static_cast<cmrs_dtype_t>(plan->val_dtype)) ||
+        plan->lds_bytes < 1 || plan->lds_bytes > 65536)
+        return fail(CMRS_ERR_INVALID_VALUE, "corrupt plan");
+    return from_hip(cmrs::launch_spmm_batched(plan, stream), "cmrs_spmm_batched");
+}
+
 cmrs_status_t cmrs_validate_csr(int32_t rows, int32_t cols, int32_t nnz, const int32_t* row_ptr,
                                 const int32_t* col_ind, int32_t* flag_out, hipStream_t stream) {
     g_last_error[0] = 0;
@@ -256,6 +401,53 @@ cmrs_status_t cmrs_calib_gather(const uint32_t* idx, int64_t n, const void* x, c
         return fail(CMRS_ERR_INVALID_VALUE, "bad calibration arguments");
     if (n > 0 && (!idx || !x)) return fail(CMRS_ERR_INVALID_VALUE, "NULL array");
     return from_hip(cmrs::launch_calib_gather(idx, n, x, x_dtype, sink, stream), "cmrs_calib_gather");
+}
+
+cmrs_status_t cmrs_features(int32_t rows, int32_t cols, int32_t nnz, const int32_t* row_ptr, const int32_t* col_ind,
+                            float* feat_out, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+    g_last_error[0] = 0;
+    if (rows < 0 || cols < 0 || nnz < 0) return fail(CMRS_ERR_INVALID_VALUE, "negative size");
+    if (!row_ptr || !feat_out || (nnz > 0 && !col_ind)) return fail(CMRS_ERR_INVALID_VALUE, "NULL pointer");
+    if (!workspace || workspace_bytes < CMRS_SEL_FEATURE_WS)
+        return fail(CMRS_ERR_WORKSPACE, "workspace of %d bytes needed", CMRS_SEL_FEATURE_WS);
+    return from_hip(cmrs::launch_features(rows, cols, nnz, row_ptr, col_ind, feat_out, static_cast<int*>(workspace),
+                                          stream),
+                    "cmrs_features");
+}
+
+cmrs_status_t cmrs_mlp_forward(int32_t batch, const float* X, const float* params, float* H1, float* H2, float* Y,
+                               hipStream_t stream) {
+    g_last_error[0] = 0;
+    if (batch < 0) return fail(CMRS_ERR_INVALID_VALUE, "negative batch");
+    if (batch == 0) return CMRS_OK;
+    if (!X || !params || !H1 || !H2 || !Y) return fail(CMRS_ERR_INVALID_VALUE, "NULL pointer");
+    return from_hip(cmrs::launch_mlp_forward(batch, X, params, H1, H2, Y, stream), "cmrs_mlp_forward");
+}
+
+cmrs_status_t cmrs_mlp_backward(int32_t batch, const float* X, const float* params, const float* H1, const float* H2,
+                                const float* dY, float* dH2, float* dH1, float* grads, hipStream_t stream) {
+    g_last_error[0] = 0;
+    if (batch <= 0) return fail(CMRS_ERR_INVALID_VALUE, "batch must be positive");
+    if (!X || !params || !H1 || !H2 || !dY || !dH2 || !dH1 || !grads) return fail(CMRS_ERR_INVALID_VALUE, "NULL pointer");
+    return from_hip(cmrs::launch_mlp_backward(batch, X, params, H1, H2, dY, dH2, dH1, grads, stream),
+                    "cmrs_mlp_backward");
+}
+
+cmrs_status_t cmrs_mse_grad(int32_t n, const float* Y, const float* T, float* dY, float scale, hipStream_t stream) {
+    g_last_error[0] = 0;
+    if (n < 0) return fail(CMRS_ERR_INVALID_VALUE, "negative size");
+    if (n == 0) return CMRS_OK;
+    if (!Y || !T || !dY) return fail(CMRS_ERR_INVALID_VALUE, "NULL pointer");
+    return from_hip(cmrs::launch_mse_grad(n, Y, T, dY, scale, stream), "cmrs_mse_grad");
+}
+
+cmrs_status_t cmrs_adam_step(int32_t n, float* params, const float* grads, float* m, float* v, float lr, float beta1,
+                             float beta2, float eps, int32_t step, hipStream_t stream) {
+    g_last_error[0] = 0;
+    if (n < 0 || step < 1) return fail(CMRS_ERR_INVALID_VALUE, "bad size or step");
+    if (n == 0) return CMRS_OK;
+    if (!params || !grads || !m || !v) return fail(CMRS_ERR_INVALID_VALUE, "NULL pointer");
+    return from_hip(cmrs::launch_adam(n, params, grads, m, v, lr, beta1, beta2, eps, step, stream), "cmrs_adam_step");
 }
 
 const char* cmrs_status_string(cmrs_status_t s) {

@@ -38,7 +38,7 @@ def test_library_exports_every_declared_symbol(C):
 
 
 def test_abi_version(C):
-    assert C.abi_version() == 1
+    assert C.abi_version() == 2
 
 
 def test_host_helpers(C):
@@ -122,3 +122,73 @@ def test_to_csr_rejects(C):
 def test_validate_rejects(C):
     assert C.lib.cmrs_validate_csr(-1, 4, 4, FAKE, FAKE, FAKE, None) == 1
     assert C.lib.cmrs_validate_csr(4, 4, 4, None, FAKE, FAKE, None) == 1
+
+
+# ----------------------------------------------------------------- multi-RHS and batches
+@pytest.mark.parametrize("nrhs,ldx,ldy,xy,group,status", [
+    (0, 4, 4, 0, 0, 1), (9, 9, 9, 0, 0, 1), (2, 1, 2, 0, 0, 1), (2, 2, 1, 0, 0, 1),
+    (2, 2, 2, 1, 0, 3),                       # fp64 values with fp32 X/Y
+    (2, 2, 2, 0, 3, 1), (2, 2, 2, 0, 64, 1),  # group not a power of two / too wide for 2 RHS
+])
+def test_spmm_rejects(C, nrhs, ldx, ldy, xy, group, status):
+    d = _mat(C)
+    assert C.lib.cmrs_spmm(ctypes.byref(d), nrhs, FAKE, ldx, FAKE + 1 << 20, ldy, xy, group, None) == status
+
+
+def test_spmm_rejects_overlap_and_accepts_empty(C):
+    d = _mat(C)
+    # X spans 4 rows x ld 8 doubles; Y starts inside it.
+    assert C.lib.cmrs_spmm(ctypes.byref(d), 2, FAKE, 8, FAKE + 100, 2, 0, 0, None) == 1
+    e = _mat(C, rows=0, nnz=0, strip_ptr=None, col_word=None, val=None)
+    assert C.lib.cmrs_spmm(ctypes.byref(e), 3, None, 3, None, 3, 0, 0, None) == 0
+
+
+def _batch(C, mats, nrhs):
+    n = len(mats)
+    return (C.CmrsMatDesc * n)(*mats), (ctypes.c_int32 * n)(*nrhs)
+
+
+def test_spmm_plan_bytes_counts_tiles(C):
+    # 1000 rows, height 4: 250 strips of 108 entries; 27 entries per slot
+    # step -> 32 slots, 2 strips per pass; 32768 / 108 -> 302 strips per
+    # tile: one tile.  Header 256 B, one 96 B descriptor, one 16 B tile.
+    m, r = _batch(C, [_mat(C, rows=1000, cols=1000, nnz=27000, height=4)], [1])
+    assert C.lib.cmrs_spmm_plan_bytes(1, m, r, None) == 256 + 96 + 16
+    tun = C.SpmmTuning(1000, 0, 0, 0)       # 1000 / 108 -> 9 -> 8 strips per tile: 32 tiles
+    assert C.lib.cmrs_spmm_plan_bytes(1, m, r, ctypes.byref(tun)) == 256 + 96 + 16 * 32
+    m2, r2 = _batch(C, [_mat(C, rows=1000, cols=1000, nnz=27000, height=4), _mat(C, rows=0, nnz=0)], [1, 8])
+    assert C.lib.cmrs_spmm_plan_bytes(2, m2, r2, None) == 256 + 2 * 96 + 16
+    bad = C.SpmmTuning(0, 0, 0, 1)           # reserved field set
+    assert C.lib.cmrs_spmm_plan_bytes(1, m, r, ctypes.byref(bad)) == 0
+    m3, r3 = _batch(C, [_mat(C)], [9])
+    assert C.lib.cmrs_spmm_plan_bytes(1, m3, r3, None) == 0
+
+
+def test_spmm_plan_rejects(C):
+    mats, nrhs = _batch(C, [_mat(C), _mat(C)], [1, 1])
+    ld = (ctypes.c_int32 * 2)(1, 1)
+    plan = C.SpmmPlanStruct()
+    X = (ctypes.c_void_p * 2)(FAKE, FAKE)               # shared X is fine
+    Y_ok = (ctypes.c_void_p * 2)(FAKE + 4096, FAKE + 8192)
+    Y_clash = (ctypes.c_void_p * 2)(FAKE + 4096, FAKE + 4096 + 16)
+    Y_on_x = (ctypes.c_void_p * 2)(FAKE + 4096, FAKE + 8)
+    def call(Y, desc=FAKE + 1 << 20, nbytes=1 << 16, tun=None):
+        return C.lib.cmrs_spmm_plan(2, mats, nrhs, X, ld, Y, ld, 0, tun, desc, nbytes, ctypes.byref(plan), None)
+    assert call(Y_clash) == 1
+    assert call(Y_on_x) == 1
+    assert call(Y_ok, nbytes=16) == 5                   # plan buffer too small
+    assert call(Y_ok, desc=FAKE + 3) == 5 or call(Y_ok, desc=FAKE + 3) == 1
+    assert call(Y_ok, tun=ctypes.byref(C.SpmmTuning(0, 3, 0, 0))) == 1
+    mixed, nr = _batch(C, [_mat(C), _mat(C, val_dtype=1)], [1, 1])
+    assert C.lib.cmrs_spmm_plan(2, mixed, nr, X, ld, Y_ok, ld, 0, None, FAKE, 1 << 16, ctypes.byref(plan),
+                                None) == 3
+
+
+def test_spmm_batched_rejects_corrupt_plan(C):
+    p = C.SpmmPlanStruct()
+    assert C.lib.cmrs_spmm_batched(ctypes.byref(p), None) == 0          # zero tiles: nothing to do
+    p.tiles, p.count, p.grid, p.waves, p.max_height, p.lds_bytes, p.desc = 3, 1, 2, 7, 4, 4096, FAKE
+    assert C.lib.cmrs_spmm_batched(ctypes.byref(p), None) == 1          # waves != 4 * grid
+    p.waves, p.max_height = 8, 3
+    assert C.lib.cmrs_spmm_batched(ctypes.byref(p), None) == 1          # height bucket not a power of two
+    assert C.lib.cmrs_spmm_batched(None, None) == 1
