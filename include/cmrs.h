@@ -225,10 +225,13 @@ cmrs_status_t cmrs_spmv_colblock(const cmrs_mat_t *A, const void *x, void *y, cm
  * y_k obeys cmrs_spmv's error bound; results are deterministic for a fixed
  * `group` (and, for batches, fixed tuning).
  *
- * cmrs_spmm: one matrix, one launch.  Lanes of a wave are split into
- * strips x entry slots x right-hand sides: `group` entry slots per strip
- * (a power of two with group * next_pow2(nrhs) <= 64; 0 chooses it from the
- * mean strip length).  X and Y must not overlap.
+ * cmrs_spmm: one matrix, one launch.  The lanes of a wave are strips x
+ * entry slots: `group` entry slots per strip (a power of two <= 64; 0
+ * chooses it from the mean strip length), every lane handling all nrhs
+ * right-hand sides of its entries with next_pow2(height) * next_pow2(nrhs)
+ * partial sums in LDS.  That LDS (64 lanes x partials x 8 bytes for fp64
+ * values, 4 otherwise) must fit 64 KiB per wave: larger height-nrhs
+ * combinations return CMRS_ERR_NOT_SUPPORTED.  X and Y must not overlap.
  */
 #define CMRS_SPMM_MAX_RHS 8
 cmrs_status_t cmrs_spmm(const cmrs_mat_t *A, int32_t nrhs, const void *X, int32_t ldx, void *Y, int32_t ldy,
@@ -267,8 +270,11 @@ typedef struct {
 } cmrs_spmm_tuning_t;
 
 typedef struct {            /* filled by cmrs_spmm_plan (host struct)          */
-    int32_t count, tiles, grid, lds_bytes;
-    int32_t val_dtype, xy_dtype, max_height, waves;
+    int32_t count, tiles;   /* matrices, work tiles                            */
+    int32_t grid, lds_bytes;/* workgroups of the launch, LDS per workgroup     */
+    int32_t val_dtype, xy_dtype;
+    int32_t max_slots;      /* largest next_pow2(height) * next_pow2(nrhs)     */
+    int32_t waves;          /* waves of the launch (1..4 per workgroup)        */
     void *desc;             /* the caller's device buffer                      */
     size_t desc_bytes;
 } cmrs_spmm_plan_t;

@@ -79,7 +79,7 @@ class SpmmTuning(ctypes.Structure):
 class SpmmPlanStruct(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int32), ("tiles", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("lds_bytes", ctypes.c_int32), ("val_dtype", ctypes.c_int32), ("xy_dtype", ctypes.c_int32),
-                ("max_height", ctypes.c_int32), ("waves", ctypes.c_int32), ("desc", ctypes.c_void_p),
+                ("max_slots", ctypes.c_int32), ("waves", ctypes.c_int32), ("desc", ctypes.c_void_p),
                 ("desc_bytes", ctypes.c_size_t)]
 
 

@@ -269,9 +269,11 @@ cmrs_status_t cmrs_spmm(const cmrs_mat_t* A, int32_t nrhs, const void* X, int32_
     g_last_error[0] = 0;
     cmrs_status_t st = check_spmm_one(A, nrhs, X, ldx, Y, ldy, xy_dtype, 0);
     if (st != CMRS_OK) return st;
-    if (group != 0 && (!is_pow2(group) || group * cmrs::next_pow2(nrhs) > 64))
-        return fail(CMRS_ERR_INVALID_VALUE, "group %d: need 0 or a power of two with group * %d <= 64", group,
-                    cmrs::next_pow2(nrhs));
+    if (group != 0 && (!is_pow2(group) || group > 64))
+        return fail(CMRS_ERR_INVALID_VALUE, "group %d: need 0 or a power of two <= 64", group);
+    if (!cmrs::spmm_fits(A->height, nrhs, A->val_dtype))
+        return fail(CMRS_ERR_NOT_SUPPORTED, "height %d with %d right-hand sides needs more than 64 KiB of LDS per wave",
+                    A->height, nrhs);
     if (A->rows == 0) return CMRS_OK;
     return from_hip(cmrs::launch_spmm(A, nrhs, X, ldx, Y, ldy, group, stream), "cmrs_spmm");
 }
@@ -297,6 +299,9 @@ static cmrs_status_t check_batch_shape(int32_t count, const cmrs_mat_t* mats, co
             return fail(CMRS_ERR_INVALID_VALUE, "matrix %d: nrhs %d outside [1, %d]", i, nrhs[i], CMRS_SPMM_MAX_RHS);
         if (mats[i].val_dtype != mats[0].val_dtype)
             return fail(CMRS_ERR_NOT_SUPPORTED, "matrix %d: value dtype differs from matrix 0", i);
+        if (!cmrs::spmm_fits(mats[i].height, nrhs[i], mats[i].val_dtype))
+            return fail(CMRS_ERR_NOT_SUPPORTED, "matrix %d: height %d with %d right-hand sides needs more than 64 KiB "
+                        "of LDS per wave", i, mats[i].height, nrhs[i]);
     }
     return CMRS_OK;
 }
@@ -366,9 +371,13 @@ cmrs_status_t cmrs_spmm_batched(const cmrs_spmm_plan_t* plan, hipStream_t stream
     if (!plan) return fail(CMRS_ERR_INVALID_VALUE, "plan is NULL");
     if (plan->tiles < 0 || plan->count < 0) return fail(CMRS_ERR_INVALID_VALUE, "corrupt plan");
     if (plan->tiles == 0) return CMRS_OK;
-    if (!plan->desc || plan->grid < 1 || plan->waves != plan->grid * 4 || !is_pow2(plan->max_height) ||
-        plan->max_height > CMRS_MAX_HEIGHT || !valid_dtype(static_cast<cmrs_dtype_t>(plan->val_dtype)) ||
-        plan->lds_bytes < 1 || plan->lds_bytes > 65536)
+    const bool waves_ok = plan->grid >= 1 && plan->waves >= plan->grid && plan->waves <= 4 * plan->grid &&
+                          plan->waves % plan->grid == 0;
+    if (!plan->desc || !waves_ok || !is_pow2(plan->max_slots) || plan->max_slots > CMRS_MAX_HEIGHT * CMRS_SPMM_MAX_RHS ||
+        !valid_dtype(static_cast<cmrs_dtype_t>(plan->val_dtype)) || plan->lds_bytes < 1 ||
+        plan->lds_bytes > 65536 ||
+        static_cast<size_t>(plan->lds_bytes) <
+            static_cast<size_t>(plan->waves / plan->grid) * plan->max_slots * 64 * (plan->val_dtype == CMRS_R64F ? 8 : 4))
         return fail(CMRS_ERR_INVALID_VALUE, "corrupt plan");
     return from_hip(cmrs::launch_spmm_batched(plan, stream), "cmrs_spmm_batched");
 }

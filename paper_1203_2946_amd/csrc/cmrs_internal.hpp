@@ -97,7 +97,7 @@ struct alignas(16) SpmmMat {
     const void* x;
     void* y;
     int32_t rows, height, bits, nrhs;
-    int32_t ldx, ldy, hb, rl_log;  // hb = next_pow2(height); 2^rl_log lanes per entry
+    int32_t ldx, ldy, hb, rb_log;     // hb = next_pow2(height), 2^rb_log = next_pow2(nrhs)
     int32_t g_log, pad0, pad1, pad2;  // 2^g_log entry slots per strip
 };
 struct SpmmTile {
@@ -105,11 +105,14 @@ struct SpmmTile {
 };
 struct SpmmPlanShape {
     int tiles;
-    int max_hb;
+    int max_slots;  // largest next_pow2(height) * next_pow2(nrhs) of the batch
     size_t bytes;
 };
 constexpr size_t kSpmmHeaderBytes = 256;
 
+size_t spmm_wave_lds_bytes(int slots, size_t acc_bytes);
+int spmm_waves_per_block(size_t wave_bytes);
+bool spmm_fits(int height, int nrhs, cmrs_dtype_t val_dtype);
 SpmmMat spmm_mat(const cmrs_mat_t* A, int nrhs, const void* X, int ldx, void* Y, int ldy, int group);
 SpmmPlanShape spmm_plan_shape(int count, const cmrs_mat_t* mats, const int* nrhs, int tile_nnz, int group,
                               std::vector<SpmmTile>* tiles_out);

@@ -1,14 +1,15 @@
 // CMRS products with several right-hand sides, single and batched.
 //
-// The hot loop is Algorithm 1 of Sec. 4 with the wave's 64 lanes split three
-// ways: S = 64 / (G * R) strips at a time, G entry slots per strip and R =
-// next_pow2(nrhs) right-hand sides per entry.  Lane (s, e, k) walks entries
-// e, e + G, ... of its strip, reads each packed word and value (the R lanes
-// of an entry read the same address: one request), gathers x_k[col] from the
-// row-major X (the R gathers of an entry are one contiguous piece) and adds
-// the product to its own partial for (row, k) in LDS.  A strip's results are
-// then the sums over its G entry slots, taken in slot order by the lane that
-// writes y_k[row].
+// The hot loop is Algorithm 1 of Sec. 4, every entry feeding all nrhs
+// right-hand sides: the wave's 64 lanes are S = 64 / G strips times G entry
+// slots; lane (s, e) walks entries e, e + G, ... of its strip, reads each
+// packed word and value once, gathers the nrhs values x_k[col] (one
+// contiguous piece of the row-major X) and adds the nrhs products to its own
+// partials for (row, k) in LDS, laid out [row * RB + k][lane] (RB =
+// next_pow2(nrhs)) so that the additions of one instruction hit 64 distinct
+// banks.  A strip's results are the sums over its G entry slots; the lane
+// that sums output (s, row, k) starts at slot (row * RB + k) mod G, which
+// spreads the reads of one instruction over distinct banks too.
 //
 // The batched path runs that body from one persistent kernel: waves take
 // work tiles (a matrix and a range of its strips) from a queue counter in the
@@ -26,9 +27,8 @@
 
 namespace cmrs {
 
-constexpr int kSpmmWaves = 4;
-constexpr int kSpmmThreads = kSpmmWaves * kWave;
-constexpr int kSpmmUnroll = 4;
+constexpr int kSpmmMaxWaves = 4;
+constexpr size_t kSpmmWaveLdsMax = 65536;
 
 template <typename T>
 __device__ inline T nt_load(const T* p) {
@@ -40,89 +40,109 @@ __device__ inline bf16_t nt_load(const bf16_t* p) {
     return v;
 }
 
-// Strips [sb, sb + S) (those below s_end) of matrix m; buf holds HB * 64
+// Strips [sb, sb + S) (those below s_end) of matrix m; buf holds HB * RB * 64
 // partials of this wave.
-template <int HB, typename VT, typename XT, typename AT>
+template <int HB, int RB, typename VT, typename XT, typename AT>
 __device__ inline void spmm_pass(const SpmmMat& m, int sb, int s_end, AT* __restrict__ buf, int lane) {
-    const int rl_log = m.rl_log, g_log = m.g_log;
-    const int R = 1 << rl_log, G = 1 << g_log;
-    const int k = lane & (R - 1);
-    const int e = (lane >> rl_log) & (G - 1);
-    const int ss = lane >> (rl_log + g_log);
-    const int s = sb + ss;
+    constexpr int U = RB >= 4 ? 4 : 8;
+    constexpr int SLOTS = HB * RB;
+    const int g_log = m.g_log;
+    const int G = 1 << g_log;
+    const int s_log = 6 - g_log;
+    const int e = lane & (G - 1);
+    const int s = sb + (lane >> g_log);
     const int bits = m.bits;
+    const int nrhs = m.nrhs;
     const uint32_t mask = (1u << bits) - 1u;
 #pragma unroll
-    for (int r = 0; r < HB; ++r) buf[r * kWave + lane] = AT(0);
+    for (int i = 0; i < SLOTS; ++i) buf[i * kWave + lane] = AT(0);
     if (s < s_end) {
         const int lo = m.strip_ptr[s], hi = m.strip_ptr[s + 1];
         const VT* __restrict__ val = static_cast<const VT*>(m.val);
         const XT* __restrict__ x = static_cast<const XT*>(m.x);
-        const bool kact = k < m.nrhs;
         const size_t ldx = static_cast<size_t>(m.ldx);
-        for (int base = lo + e; base < hi; base += kSpmmUnroll * G) {
-            uint32_t w[kSpmmUnroll];
-            VT v[kSpmmUnroll];
-            XT xv[kSpmmUnroll];
+        for (int base = lo + e; base < hi; base += U * G) {
+            // Out-of-range entries are clamped to the last one of the strip
+            // (a valid address) and their products dropped, so every load
+            // of the step is issued without a branch.
+            uint32_t w[U];
+            VT v[U];
+            XT xv[U][RB];
 #pragma unroll
-            for (int u = 0; u < kSpmmUnroll; ++u) {
-                const int j = base + u * G;
-                if (j < hi) {
-                    w[u] = nt_load(m.word + j);
-                    v[u] = nt_load(val + j);
-                }
+            for (int u = 0; u < U; ++u) {
+                const int j = min(base + u * G, hi - 1);
+                w[u] = nt_load(m.word + j);
+                v[u] = nt_load(val + j);
             }
 #pragma unroll
-            for (int u = 0; u < kSpmmUnroll; ++u) {
-                const int j = base + u * G;
-                if (j < hi && kact) xv[u] = x[static_cast<size_t>(w[u] >> bits) * ldx + k];
+            for (int u = 0; u < U; ++u) {
+                const XT* xr = x + static_cast<size_t>(w[u] >> bits) * ldx;
+#pragma unroll
+                for (int k = 0; k < RB; ++k) xv[u][k] = xr[k < nrhs ? k : 0];
             }
 #pragma unroll
-            for (int u = 0; u < kSpmmUnroll; ++u) {
-                const int j = base + u * G;
-                if (j < hi && kact) {
-                    const AT p = static_cast<AT>(ValTraits<VT>::widen(v[u])) * static_cast<AT>(xv[u]);
-                    atomicAdd(&buf[static_cast<int>(w[u] & mask & (HB - 1)) * kWave + lane], p);
+            for (int u = 0; u < U; ++u) {
+                if (base + u * G < hi) {
+                    const AT a = static_cast<AT>(ValTraits<VT>::widen(v[u]));
+                    AT* slot = buf + static_cast<int>(w[u] & mask & (HB - 1)) * RB * kWave + lane;
+#pragma unroll
+                    for (int k = 0; k < RB; ++k)
+                        if (k < nrhs) lds_add(slot + k * kWave, a * static_cast<AT>(xv[u][k]));
                 }
             }
         }
     }
     wave_lds_sync();
-    // Outputs o = (strip slot, row, k) with k fastest; each sums the G entry
-    // slots of its strip in slot order.
-    const int nout = kWave * HB >> g_log;
+    // Output o: strip slot so = o mod S (fastest), partial i = o / S with
+    // i = row * RB + k; it sums the G entry slots starting at slot i mod G.
+    constexpr int NOUT_PER_S = SLOTS;
+    const int nout = NOUT_PER_S << s_log;
     XT* __restrict__ y = static_cast<XT*>(m.y);
     const size_t ldy = static_cast<size_t>(m.ldy);
     for (int o = lane; o < nout; o += kWave) {
-        const int kk = o & (R - 1);
-        const int rr = (o >> rl_log) & (HB - 1);
-        const int so = o >> rl_log >> __builtin_ctz(HB);
-        const AT* p = buf + rr * kWave + ((so << g_log) << rl_log) + kk;
-        AT sum = p[0];
-        for (int q = 1; q < G; ++q) sum += p[q << rl_log];
+        const int so = o & ((1 << s_log) - 1);
+        const int i = o >> s_log;
+        const int k = i & (RB - 1);
+        const int rr = i / RB;
+        const AT* p = buf + i * kWave + (so << g_log);
+        AT sum = AT(0);
+        for (int q = 0; q < G; ++q) sum += p[(q + i) & (G - 1)];
         const int strip = sb + so;
         const long long row = static_cast<long long>(strip) * m.height + rr;
-        if (strip < s_end && rr < m.height && row < m.rows && kk < m.nrhs)
-            y[static_cast<size_t>(row) * ldy + kk] = static_cast<XT>(sum);
+        if (strip < s_end && rr < m.height && row < m.rows && k < nrhs)
+            y[static_cast<size_t>(row) * ldy + k] = static_cast<XT>(sum);
     }
     wave_lds_sync();
 }
 
-template <int HB, typename VT, typename XT, typename AT>
-__global__ __launch_bounds__(kSpmmThreads) void spmm_kernel(SpmmMat m, int strips) {
-    __shared__ AT buf[kSpmmWaves][HB * kWave];
+template <int HB, int RB, typename VT, typename XT, typename AT>
+__global__ __launch_bounds__(kSpmmMaxWaves * kWave) void spmm_kernel(SpmmMat m, int strips) {
+    extern __shared__ __align__(16) unsigned char spmm_lds[];
+    AT* buf = reinterpret_cast<AT*>(spmm_lds);
     const int lane = lane_id();
+    const int wpb = static_cast<int>(blockDim.x) / kWave;
     const int wave = uniform(static_cast<int>(threadIdx.x) / kWave);
-    const int S = kWave >> (m.rl_log + m.g_log);
-    const long long sb = (static_cast<long long>(xcd_logical_block(blockIdx.x, gridDim.x)) * kSpmmWaves + wave) * S;
+    const int s_log = 6 - m.g_log;
+    const long long sb =
+        (static_cast<long long>(xcd_logical_block(blockIdx.x, gridDim.x)) * wpb + wave) << s_log;
     if (sb >= strips) return;
-    spmm_pass<HB, VT, XT, AT>(m, static_cast<int>(sb), strips, buf[wave], lane);
+    spmm_pass<HB, RB, VT, XT, AT>(m, static_cast<int>(sb), strips, buf + wave * (HB * RB * kWave), lane);
+}
+
+template <int HB, int RB, typename VT, typename XT, typename AT>
+__device__ inline void spmm_tile(const SpmmMat& m, int s0, int s1, AT* buf, int lane) {
+    const int S = kWave >> m.g_log;
+    for (int sb = s0; sb < s1; sb += S) spmm_pass<HB, RB, VT, XT, AT>(m, sb, s1, buf, lane);
 }
 
 template <int HB, typename VT, typename XT, typename AT>
-__device__ inline void spmm_tile(const SpmmMat& m, int s0, int s1, AT* buf, int lane) {
-    const int S = kWave >> (m.rl_log + m.g_log);
-    for (int sb = s0; sb < s1; sb += S) spmm_pass<HB, VT, XT, AT>(m, sb, s1, buf, lane);
+__device__ inline void spmm_tile_rb(const SpmmMat& m, int s0, int s1, AT* buf, int lane) {
+    switch (m.rb_log) {
+        case 0: spmm_tile<HB, 1, VT, XT, AT>(m, s0, s1, buf, lane); break;
+        case 1: spmm_tile<HB, 2, VT, XT, AT>(m, s0, s1, buf, lane); break;
+        case 2: spmm_tile<HB, 4, VT, XT, AT>(m, s0, s1, buf, lane); break;
+        default: spmm_tile<HB, 8, VT, XT, AT>(m, s0, s1, buf, lane); break;
+    }
 }
 
 // queue[0]: next tile; queue[kQueueDone]: waves finished.  Both are zero at
@@ -130,14 +150,13 @@ __device__ inline void spmm_tile(const SpmmMat& m, int s0, int s1, AT* buf, int 
 constexpr int kQueueDone = 16;
 
 template <typename VT, typename XT, typename AT>
-__global__ __launch_bounds__(kSpmmThreads) void spmm_persistent_kernel(const SpmmMat* __restrict__ mats,
-                                                                       const SpmmTile* __restrict__ tiles,
-                                                                       int ntiles, unsigned* __restrict__ queue,
-                                                                       int waves_total, int wave_slots) {
-    extern __shared__ __align__(16) unsigned char spmm_smem[];
+__global__ __launch_bounds__(kSpmmMaxWaves * kWave) void spmm_persistent_kernel(
+    const SpmmMat* __restrict__ mats, const SpmmTile* __restrict__ tiles, int ntiles, unsigned* __restrict__ queue,
+    int waves_total, int wave_slots) {
+    extern __shared__ __align__(16) unsigned char spmm_lds[];
     const int lane = lane_id();
     const int wave = uniform(static_cast<int>(threadIdx.x) / kWave);
-    AT* buf = reinterpret_cast<AT*>(spmm_smem) + static_cast<size_t>(wave) * wave_slots;
+    AT* buf = reinterpret_cast<AT*>(spmm_lds) + static_cast<size_t>(wave) * wave_slots;
     for (;;) {
         unsigned t = 0;
         if (lane == 0) t = __hip_atomic_fetch_add(&queue[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -146,12 +165,12 @@ __global__ __launch_bounds__(kSpmmThreads) void spmm_persistent_kernel(const Spm
         const SpmmTile tile = tiles[t];
         const SpmmMat m = mats[tile.mat];
         switch (m.hb) {
-            case 1: spmm_tile<1, VT, XT, AT>(m, tile.s0, tile.s1, buf, lane); break;
-            case 2: spmm_tile<2, VT, XT, AT>(m, tile.s0, tile.s1, buf, lane); break;
-            case 4: spmm_tile<4, VT, XT, AT>(m, tile.s0, tile.s1, buf, lane); break;
-            case 8: spmm_tile<8, VT, XT, AT>(m, tile.s0, tile.s1, buf, lane); break;
-            case 16: spmm_tile<16, VT, XT, AT>(m, tile.s0, tile.s1, buf, lane); break;
-            default: spmm_tile<32, VT, XT, AT>(m, tile.s0, tile.s1, buf, lane); break;
+            case 1: spmm_tile_rb<1, VT, XT, AT>(m, tile.s0, tile.s1, buf, lane); break;
+            case 2: spmm_tile_rb<2, VT, XT, AT>(m, tile.s0, tile.s1, buf, lane); break;
+            case 4: spmm_tile_rb<4, VT, XT, AT>(m, tile.s0, tile.s1, buf, lane); break;
+            case 8: spmm_tile_rb<8, VT, XT, AT>(m, tile.s0, tile.s1, buf, lane); break;
+            case 16: spmm_tile_rb<16, VT, XT, AT>(m, tile.s0, tile.s1, buf, lane); break;
+            default: spmm_tile_rb<32, VT, XT, AT>(m, tile.s0, tile.s1, buf, lane); break;
         }
     }
     // Every wave has taken its last ticket before it counts itself out, so
@@ -176,23 +195,56 @@ int ilog2(int v) {
     return l;
 }
 
+template <int HB, int RB, typename VT, typename XT, typename AT>
+void launch_spmm_hb_rb(const SpmmMat& m, int strips, int wpb, size_t lds, hipStream_t stream) {
+    const int S = kWave >> m.g_log;
+    const long long waves = (static_cast<long long>(strips) + S - 1) / S;
+    const int grid = static_cast<int>((waves + wpb - 1) / wpb);
+    hipLaunchKernelGGL((spmm_kernel<HB, RB, VT, XT, AT>), dim3(grid), dim3(wpb * kWave), lds, stream, m, strips);
+}
+
+template <int HB, typename VT, typename XT, typename AT>
+void launch_spmm_hb(const SpmmMat& m, int strips, int wpb, size_t lds, hipStream_t stream) {
+    switch (m.rb_log) {
+        case 0: launch_spmm_hb_rb<HB, 1, VT, XT, AT>(m, strips, wpb, lds, stream); break;
+        case 1: launch_spmm_hb_rb<HB, 2, VT, XT, AT>(m, strips, wpb, lds, stream); break;
+        case 2: launch_spmm_hb_rb<HB, 4, VT, XT, AT>(m, strips, wpb, lds, stream); break;
+        default: launch_spmm_hb_rb<HB, 8, VT, XT, AT>(m, strips, wpb, lds, stream); break;
+    }
+}
+
 template <typename VT, typename XT, typename AT>
 hipError_t launch_spmm_typed(const SpmmMat& m, int strips, hipStream_t stream) {
-    const int S = kWave >> (m.rl_log + m.g_log);
-    const long long waves = (static_cast<long long>(strips) + S - 1) / S;
-    const int grid = static_cast<int>((waves + kSpmmWaves - 1) / kSpmmWaves);
+    const size_t wave_bytes = spmm_wave_lds_bytes(m.hb << m.rb_log, sizeof(AT));
+    const int wpb = spmm_waves_per_block(wave_bytes);
+    const size_t lds = wave_bytes * wpb;
     switch (m.hb) {
-        case 1: hipLaunchKernelGGL((spmm_kernel<1, VT, XT, AT>), dim3(grid), dim3(kSpmmThreads), 0, stream, m, strips); break;
-        case 2: hipLaunchKernelGGL((spmm_kernel<2, VT, XT, AT>), dim3(grid), dim3(kSpmmThreads), 0, stream, m, strips); break;
-        case 4: hipLaunchKernelGGL((spmm_kernel<4, VT, XT, AT>), dim3(grid), dim3(kSpmmThreads), 0, stream, m, strips); break;
-        case 8: hipLaunchKernelGGL((spmm_kernel<8, VT, XT, AT>), dim3(grid), dim3(kSpmmThreads), 0, stream, m, strips); break;
-        case 16: hipLaunchKernelGGL((spmm_kernel<16, VT, XT, AT>), dim3(grid), dim3(kSpmmThreads), 0, stream, m, strips); break;
-        default: hipLaunchKernelGGL((spmm_kernel<32, VT, XT, AT>), dim3(grid), dim3(kSpmmThreads), 0, stream, m, strips); break;
+        case 1: launch_spmm_hb<1, VT, XT, AT>(m, strips, wpb, lds, stream); break;
+        case 2: launch_spmm_hb<2, VT, XT, AT>(m, strips, wpb, lds, stream); break;
+        case 4: launch_spmm_hb<4, VT, XT, AT>(m, strips, wpb, lds, stream); break;
+        case 8: launch_spmm_hb<8, VT, XT, AT>(m, strips, wpb, lds, stream); break;
+        case 16: launch_spmm_hb<16, VT, XT, AT>(m, strips, wpb, lds, stream); break;
+        default: launch_spmm_hb<32, VT, XT, AT>(m, strips, wpb, lds, stream); break;
     }
     return hipGetLastError();
 }
 
 }  // namespace
+
+size_t spmm_wave_lds_bytes(int slots, size_t acc_bytes) {
+    return static_cast<size_t>(slots) * kWave * acc_bytes;
+}
+
+int spmm_waves_per_block(size_t wave_bytes) {
+    if (wave_bytes == 0) return kSpmmMaxWaves;
+    const size_t w = kSpmmWaveLdsMax / wave_bytes;
+    return static_cast<int>(std::max<size_t>(1, std::min<size_t>(kSpmmMaxWaves, w)));
+}
+
+bool spmm_fits(int height, int nrhs, cmrs_dtype_t val_dtype) {
+    const size_t at = val_dtype == CMRS_R64F ? 8 : 4;
+    return spmm_wave_lds_bytes(next_pow2(height) * next_pow2(nrhs), at) <= kSpmmWaveLdsMax;
+}
 
 SpmmMat spmm_mat(const cmrs_mat_t* A, int nrhs, const void* X, int ldx, void* Y, int ldy, int group) {
     SpmmMat m{};
@@ -208,16 +260,16 @@ SpmmMat spmm_mat(const cmrs_mat_t* A, int nrhs, const void* X, int ldx, void* Y,
     m.ldx = ldx;
     m.ldy = ldy;
     m.hb = next_pow2(A->height);
-    m.rl_log = ilog2(nrhs);
-    const int gmax = kWave >> m.rl_log;
+    m.rb_log = ilog2(nrhs);
     int g = group;
     if (g <= 0) {
         // Enough entry slots that one unrolled step covers the mean strip.
+        const int unroll = (1 << m.rb_log) >= 4 ? 4 : 8;
         const int strips = (A->rows + A->height - 1) / A->height;
         const double mean = strips > 0 ? static_cast<double>(A->nnz) / strips : 0.0;
-        g = next_pow2(static_cast<int>(std::min(64.0, std::max(1.0, mean / kSpmmUnroll))));
+        g = next_pow2(static_cast<int>(std::min(64.0, std::max(1.0, mean / unroll))));
     }
-    if (g > gmax) g = gmax;
+    if (g > kWave) g = kWave;
     m.g_log = ilog2(g);
     return m;
 }
@@ -238,18 +290,29 @@ SpmmPlanShape spmm_plan_shape(int count, const cmrs_mat_t* mats, const int* nrhs
                               std::vector<SpmmTile>* tiles_out) {
     SpmmPlanShape sh{};
     const int target = tile_nnz > 0 ? tile_nnz : 32768;
+    // Tiles grouped by (height bucket, right-hand-side bucket), so that waves
+    // running at the same time mostly execute the same code.
+    std::vector<std::pair<int, int>> order;
     for (int i = 0; i < count; ++i) {
+        const SpmmMat m = spmm_mat(&mats[i], nrhs[i], nullptr, nrhs[i], nullptr, nrhs[i], group);
+        order.push_back({m.hb * 16 + m.rb_log, i});
+        sh.max_slots = std::max(sh.max_slots, m.hb << m.rb_log);
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [](const std::pair<int, int>& a, const std::pair<int, int>& b) { return a.first < b.first; });
+    for (const auto& oi : order) {
+        const int i = oi.second;
         const cmrs_mat_t& A = mats[i];
         const SpmmMat m = spmm_mat(&A, nrhs[i], nullptr, nrhs[i], nullptr, nrhs[i], group);
-        sh.max_hb = std::max(sh.max_hb, m.hb);
         const long long strips = (static_cast<long long>(A.rows) + A.height - 1) / A.height;
         if (strips == 0) continue;
-        const int S = kWave >> (m.rl_log + m.g_log);
+        const int S = kWave >> m.g_log;
         const double per_strip = std::max(1.0, static_cast<double>(A.nnz) / static_cast<double>(strips));
         long long T = static_cast<long long>(target / per_strip) / S * S;
         if (T < S) T = S;
         for (long long s0 = 0; s0 < strips; s0 += T) {
-            if (tiles_out) tiles_out->push_back(SpmmTile{i, static_cast<int>(s0), static_cast<int>(std::min(strips, s0 + T)), 0});
+            if (tiles_out)
+                tiles_out->push_back(SpmmTile{i, static_cast<int>(s0), static_cast<int>(std::min(strips, s0 + T)), 0});
             ++sh.tiles;
         }
     }
@@ -266,24 +329,26 @@ hipError_t build_spmm_plan(int count, const cmrs_mat_t* mats, const int* nrhs, c
     SpmmMat* md = reinterpret_cast<SpmmMat*>(image.data() + kSpmmHeaderBytes);
     for (int i = 0; i < count; ++i) md[i] = spmm_mat(&mats[i], nrhs[i], X[i], ldx[i], Y[i], ldy[i], group);
     if (!tiles.empty())
-        memcpy(image.data() + kSpmmHeaderBytes + sizeof(SpmmMat) * count, tiles.data(), sizeof(SpmmTile) * tiles.size());
+        memcpy(image.data() + kSpmmHeaderBytes + sizeof(SpmmMat) * count, tiles.data(),
+               sizeof(SpmmTile) * tiles.size());
     int dev = 0, cus = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    const int bpc = blocks_per_cu > 0 ? blocks_per_cu : 4;
-    const long long want_blocks = (static_cast<long long>(sh.tiles) + kSpmmWaves - 1) / kSpmmWaves;
-    const int grid = static_cast<int>(std::max(1LL, std::min(static_cast<long long>(cus) * bpc, want_blocks)));
     const size_t at = count > 0 && mats[0].val_dtype == CMRS_R64F ? 8 : 4;
-    const int wave_slots = std::max(1, sh.max_hb) * kWave;
+    const size_t wave_bytes = spmm_wave_lds_bytes(std::max(1, sh.max_slots), at);
+    const int wpb = spmm_waves_per_block(wave_bytes);
+    const int bpc = blocks_per_cu > 0 ? blocks_per_cu : 4;
+    const long long want_blocks = (static_cast<long long>(sh.tiles) + wpb - 1) / wpb;
+    const int grid = static_cast<int>(std::max(1LL, std::min(static_cast<long long>(cus) * bpc, want_blocks)));
     plan->count = count;
     plan->tiles = sh.tiles;
     plan->grid = sh.tiles > 0 ? grid : 0;
-    plan->lds_bytes = static_cast<int>(at * wave_slots * kSpmmWaves);
+    plan->lds_bytes = static_cast<int>(wave_bytes * wpb);
     plan->val_dtype = count > 0 ? mats[0].val_dtype : CMRS_R64F;
     plan->xy_dtype = xy_dtype;
-    plan->max_height = sh.max_hb;
-    plan->waves = plan->grid * kSpmmWaves;
+    plan->max_slots = std::max(1, sh.max_slots);
+    plan->waves = plan->grid * wpb;
     plan->desc = desc;
     plan->desc_bytes = sh.bytes;
     e = hipMemcpyAsync(desc, image.data(), sh.bytes, hipMemcpyHostToDevice, stream);
@@ -296,14 +361,16 @@ hipError_t launch_spmm_batched(const cmrs_spmm_plan_t* plan, hipStream_t stream)
     unsigned char* base = static_cast<unsigned char*>(plan->desc);
     unsigned* queue = reinterpret_cast<unsigned*>(base);
     const SpmmMat* mats = reinterpret_cast<const SpmmMat*>(base + kSpmmHeaderBytes);
-    const SpmmTile* tiles = reinterpret_cast<const SpmmTile*>(base + kSpmmHeaderBytes + sizeof(SpmmMat) * plan->count);
-    const int wave_slots = plan->max_height * kWave;
-    const dim3 grid(plan->grid), block(kSpmmThreads);
+    const SpmmTile* tiles =
+        reinterpret_cast<const SpmmTile*>(base + kSpmmHeaderBytes + sizeof(SpmmMat) * plan->count);
+    const int wave_slots = plan->max_slots * kWave;
+    const int wpb = plan->waves / plan->grid;
+    const dim3 grid(plan->grid), block(wpb * kWave);
     const size_t lds = static_cast<size_t>(plan->lds_bytes);
     switch (plan->val_dtype) {
         case CMRS_R64F:
-            hipLaunchKernelGGL((spmm_persistent_kernel<double, double, double>), grid, block, lds, stream, mats, tiles,
-                               plan->tiles, queue, plan->waves, wave_slots);
+            hipLaunchKernelGGL((spmm_persistent_kernel<double, double, double>), grid, block, lds, stream, mats,
+                               tiles, plan->tiles, queue, plan->waves, wave_slots);
             break;
         case CMRS_R32F:
             hipLaunchKernelGGL((spmm_persistent_kernel<float, float, float>), grid, block, lds, stream, mats, tiles,

@@ -79,7 +79,7 @@ struct LdsAcc {
         for (int r = 0; r < HB; ++r) b[r * kWave + lane] = AT(0);
     }
     __device__ inline void add(uint32_t r, int lane, AT p) {
-        atomicAdd(&b[(static_cast<int>(r) & (HB - 1)) * kWave + lane], p);
+        lds_add(&b[(static_cast<int>(r) & (HB - 1)) * kWave + lane], p);
     }
     // Row sums; lane l holds the sum of row l / (64 / HB).
     __device__ inline AT finish(int lane) {
@@ -133,26 +133,23 @@ __device__ inline void accumulate_run(Acc& acc, int lo, int hi, int bits, const 
                                       const VT* __restrict__ val, const XT* __restrict__ x, int lane) {
     const uint32_t mask = (1u << bits) - 1u;
     for (int base = lo; base < hi; base += U * kWave) {
+        // Entries past the run are clamped to its last entry (a valid
+        // address) and their products dropped: every load of the step is
+        // issued without a branch.
         uint32_t w[U];
         VT v[U];
         XT xv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int j = base + u * kWave + lane;
-            if (j < hi) {
-                w[u] = stream_load<NT>(word + j);
-                v[u] = stream_load<NT>(val + j);
-            }
+            const int j = min(base + u * kWave + lane, hi - 1);
+            w[u] = stream_load<NT>(word + j);
+            v[u] = stream_load<NT>(val + j);
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int j = base + u * kWave + lane;
-            if (j < hi) xv[u] = x[w[u] >> bits];
-        }
+        for (int u = 0; u < U; ++u) xv[u] = x[w[u] >> bits];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int j = base + u * kWave + lane;
-            if (j < hi) {
+            if (base + u * kWave + lane < hi) {
                 const AT p = static_cast<AT>(ValTraits<VT>::widen(v[u])) * static_cast<AT>(xv[u]);
                 acc.add(w[u] & mask, lane, p);
             }
@@ -262,24 +259,19 @@ __device__ inline void group_runs(int lo, int hi, int long_len, int bits, const 
             XT xv[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int j = j0 + u * G;
-                if (j < hi) {
-                    w[u] = stream_load<NT>(word + j);
-                    v[u] = stream_load<NT>(val + j);
-                }
+                const int j = min(j0 + u * G, hi - 1);
+                w[u] = stream_load<NT>(word + j);
+                v[u] = stream_load<NT>(val + j);
             }
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int j = j0 + u * G;
-                if (j < hi) xv[u] = x[w[u] >> bits];
-            }
+            for (int u = 0; u < U; ++u) xv[u] = x[w[u] >> bits];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int j = j0 + u * G;
                 if (j < hi) {
                     const AT p = static_cast<AT>(ValTraits<VT>::widen(v[u])) * static_cast<AT>(xv[u]);
                     const int r = static_cast<int>(w[u] & mask) & (HB - 1);
-                    atomicAdd(&b[(g * HB + r) * G + q], p);
+                    lds_add(&b[(g * HB + r) * G + q], p);
                 }
             }
         }

@@ -109,3 +109,25 @@ def dblock(n, g, block=32, per_row=None):
 
 def generate(family, n, g):
     return {"stencil": stencil, "banded": banded, "poisson": poisson, "zipf": zipf, "dblock": dblock}[family](n, g)
+
+
+def batched_workload(seed: int = 0, count: int = 256, lo: int = 10_000, hi: int = 500_000, dev="cuda"):
+    """The uneven batch: `count` matrices with rows log-uniform in [lo, hi],
+    alternately 3-D 27-point stencils and band matrices (bandwidth uniform in
+    8..64, 60 % fill), values N(0,1), each with 1..8 right-hand sides.
+    Returns a list of (family, row_ptr, col_ind, val, cols, nrhs)."""
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    out = []
+    for i in range(count):
+        u = torch.rand(2, generator=g, device=dev).tolist()
+        n = int(round(math.exp(math.log(lo) + u[0] * (math.log(hi) - math.log(lo)))))
+        nrhs = 1 + min(7, int(u[1] * 8))
+        if i % 2 == 0:
+            rp, ci, val, cols = stencil(n, g)
+            fam = "stencil"
+        else:
+            rp, ci, val, cols = banded(n, g)
+            fam = "banded"
+        out.append((fam, rp, ci, val, cols, nrhs))
+    return out

@@ -128,11 +128,19 @@ def test_validate_rejects(C):
 @pytest.mark.parametrize("nrhs,ldx,ldy,xy,group,status", [
     (0, 4, 4, 0, 0, 1), (9, 9, 9, 0, 0, 1), (2, 1, 2, 0, 0, 1), (2, 2, 1, 0, 0, 1),
     (2, 2, 2, 1, 0, 3),                       # fp64 values with fp32 X/Y
-    (2, 2, 2, 0, 3, 1), (2, 2, 2, 0, 64, 1),  # group not a power of two / too wide for 2 RHS
+    (2, 2, 2, 0, 3, 1), (2, 2, 2, 0, 128, 1), # group not a power of two / above 64
 ])
 def test_spmm_rejects(C, nrhs, ldx, ldy, xy, group, status):
     d = _mat(C)
     assert C.lib.cmrs_spmm(ctypes.byref(d), nrhs, FAKE, ldx, FAKE + 1 << 20, ldy, xy, group, None) == status
+
+
+def test_spmm_lds_limit(C):
+    # 32 rows x 8 right-hand sides x 64 lanes of fp64 partials = 128 KiB per wave.
+    big = _mat(C, rows=64, cols=64, height=32, bits=5)
+    assert C.lib.cmrs_spmm(ctypes.byref(big), 8, FAKE, 8, FAKE + (1 << 20), 8, 0, 0, None) == 3
+    m, r = _batch(C, [big], [8])
+    assert C.lib.cmrs_spmm_plan_bytes(1, m, r, None) == 0
 
 
 def test_spmm_rejects_overlap_and_accepts_empty(C):
@@ -149,9 +157,10 @@ def _batch(C, mats, nrhs):
 
 
 def test_spmm_plan_bytes_counts_tiles(C):
-    # 1000 rows, height 4: 250 strips of 108 entries; 27 entries per slot
-    # step -> 32 slots, 2 strips per pass; 32768 / 108 -> 302 strips per
-    # tile: one tile.  Header 256 B, one 96 B descriptor, one 16 B tile.
+    # 1000 rows, height 4: 250 strips of 108 entries; one right-hand side
+    # unrolls 8 entries per slot: 108 / 8 -> 16 slots, 4 strips per pass;
+    # 32768 / 108 -> 300 strips per tile: one tile.  Header 256 B, one 96 B
+    # descriptor, one 16 B tile.
     m, r = _batch(C, [_mat(C, rows=1000, cols=1000, nnz=27000, height=4)], [1])
     assert C.lib.cmrs_spmm_plan_bytes(1, m, r, None) == 256 + 96 + 16
     tun = C.SpmmTuning(1000, 0, 0, 0)       # 1000 / 108 -> 9 -> 8 strips per tile: 32 tiles
@@ -187,8 +196,10 @@ def test_spmm_plan_rejects(C):
 def test_spmm_batched_rejects_corrupt_plan(C):
     p = C.SpmmPlanStruct()
     assert C.lib.cmrs_spmm_batched(ctypes.byref(p), None) == 0          # zero tiles: nothing to do
-    p.tiles, p.count, p.grid, p.waves, p.max_height, p.lds_bytes, p.desc = 3, 1, 2, 7, 4, 4096, FAKE
-    assert C.lib.cmrs_spmm_batched(ctypes.byref(p), None) == 1          # waves != 4 * grid
-    p.waves, p.max_height = 8, 3
-    assert C.lib.cmrs_spmm_batched(ctypes.byref(p), None) == 1          # height bucket not a power of two
+    p.tiles, p.count, p.grid, p.waves, p.max_slots, p.lds_bytes, p.desc = 3, 1, 2, 7, 4, 4 * 64 * 8 * 4, FAKE
+    assert C.lib.cmrs_spmm_batched(ctypes.byref(p), None) == 1          # waves not a multiple of grid
+    p.waves, p.max_slots = 8, 3
+    assert C.lib.cmrs_spmm_batched(ctypes.byref(p), None) == 1          # slot count not a power of two
+    p.max_slots, p.lds_bytes = 4, 1024
+    assert C.lib.cmrs_spmm_batched(ctypes.byref(p), None) == 1          # LDS below 4 waves x 4 slots x 64 x 8 B
     assert C.lib.cmrs_spmm_batched(None, None) == 1
