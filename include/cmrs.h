@@ -288,6 +288,48 @@ cmrs_status_t cmrs_spmm_plan(int32_t count, const cmrs_mat_t *mats, const int32_
 cmrs_status_t cmrs_spmm_batched(const cmrs_spmm_plan_t *plan, hipStream_t stream);
 
 /*
+ * Modified CMRS of Sec. 6.7 ("padded"): strips padded with explicit zeros to
+ * whole chunks of 64 entries, every row contributing at most 8 contiguous
+ * entries to a chunk, so that the SpMV needs only 8 copies of a strip's row
+ * sums per wave (lane l adds into copy l mod 8) and every load is an aligned
+ * 64-lane access.  The paper gives the constraints; the arrangement used
+ * here takes, chunk after chunk, min(8, entries left) entries of every row
+ * in CSR order, rows with more entries left first (ties: lower row), until
+ * the chunk is full; the remaining slots are padding.  A padding entry has
+ * RowInStrip = height, column 0 and value +0 and is skipped by the kernel.
+ * The packed RowInStrip field is cmrs_padded_bits(height) wide (one more
+ * bit than cmrs_bits_for_height when height is a power of two >= 16).
+ * Padding can multiply the stored entries (a row of L entries needs at
+ * least L/8 chunks); the plan returns the padded size so the caller can
+ * weigh the memory overhead.
+ *
+ * cmrs_padded_plan: counts the chunks of every strip and writes
+ *   strip_ptr_out[strips+1] (entry offsets, multiples of 64) and
+ *   *padded_nnz_out (host); synchronises `stream` to return the size.
+ *   CMRS_ERR_INDEX_OVERFLOW when the padded size exceeds INT32_MAX (the
+ *   size is still returned).  Workspace: cmrs_padded_plan_workspace() bytes,
+ *   8-byte aligned.
+ * cmrs_padded_from_csr: fills col_word_out / val_out (padded_nnz entries)
+ *   for canonical or any CSR; entries keep their CSR order within a row.
+ *   Outputs may not overlap the inputs.
+ * cmrs_padded_spmv: y = A x for a padded matrix: A->strip_ptr from the plan,
+ *   A->nnz = padded_nnz, A->bits = cmrs_padded_bits(height), A->sorted
+ *   ignored.  Every row of y is written (empty rows +0); error bound and
+ *   dtypes as for cmrs_spmv.
+ */
+int32_t cmrs_padded_bits(int32_t height);
+size_t cmrs_padded_plan_workspace(int32_t rows, int32_t height);
+cmrs_status_t cmrs_padded_plan(int32_t rows, int32_t nnz, const int32_t *row_ptr, int32_t height,
+                               int32_t *strip_ptr_out, int64_t *padded_nnz_out, void *workspace,
+                               size_t workspace_bytes, hipStream_t stream);
+cmrs_status_t cmrs_padded_from_csr(int32_t rows, int32_t cols, int32_t nnz, const int32_t *row_ptr,
+                                   const int32_t *col_ind, const void *val_in, cmrs_dtype_t dtype, int32_t height,
+                                   const int32_t *strip_ptr, int32_t padded_nnz, uint32_t *col_word_out,
+                                   void *val_out, hipStream_t stream);
+cmrs_status_t cmrs_padded_spmv(const cmrs_mat_t *A, const void *x, void *y, cmrs_dtype_t xy_dtype,
+                               hipStream_t stream);
+
+/*
  * Device check of CSR validity: writes *flag_out = 0 when row_ptr[0] == 0,
  * row_ptr is non-decreasing, row_ptr[rows] == nnz and every column is in
  * [0, cols); otherwise a non-zero bit mask (1: row_ptr[0] or row_ptr[rows]

@@ -94,6 +94,14 @@ lib.cmrs_spmm_plan.argtypes = [_i32, _DP, _PI32, _PVP, _PI32, _PVP, _PI32, ctype
 lib.cmrs_spmm_plan.restype = ctypes.c_int
 lib.cmrs_spmm_batched.argtypes = [ctypes.POINTER(SpmmPlanStruct), _vp]
 lib.cmrs_spmm_batched.restype = ctypes.c_int
+lib.cmrs_padded_bits.argtypes, lib.cmrs_padded_bits.restype = [_i32], _i32
+lib.cmrs_padded_plan_workspace.argtypes, lib.cmrs_padded_plan_workspace.restype = [_i32, _i32], _sz
+lib.cmrs_padded_plan.argtypes = [_i32, _i32, _vp, _i32, _vp, ctypes.POINTER(ctypes.c_int64), _vp, _sz, _vp]
+lib.cmrs_padded_plan.restype = ctypes.c_int
+lib.cmrs_padded_from_csr.argtypes = [_i32, _i32, _i32, _vp, _vp, _vp, ctypes.c_int, _i32, _vp, _i32, _vp, _vp, _vp]
+lib.cmrs_padded_from_csr.restype = ctypes.c_int
+lib.cmrs_padded_spmv.argtypes = [_DP, _vp, _vp, ctypes.c_int, _vp]
+lib.cmrs_padded_spmv.restype = ctypes.c_int
 lib.cmrs_features.argtypes = [_i32, _i32, _i32, _vp, _vp, _vp, _vp, _sz, _vp]
 lib.cmrs_features.restype = ctypes.c_int
 lib.cmrs_mlp_forward.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -113,6 +121,8 @@ EXPORTED = ["cmrs_abi_version", "cmrs_num_strips", "cmrs_bits_for_height", "cmrs
             "cmrs_from_csr", "cmrs_to_csr_workspace", "cmrs_to_csr", "cmrs_spmv", "cmrs_validate_csr",
             "cmrs_colblock_plan_bytes", "cmrs_colblock_plan", "cmrs_spmv_colblock_workspace", "cmrs_spmv_colblock",
             "cmrs_spmm", "cmrs_spmm_plan_bytes", "cmrs_spmm_plan", "cmrs_spmm_batched",
+            "cmrs_padded_bits", "cmrs_padded_plan_workspace", "cmrs_padded_plan", "cmrs_padded_from_csr",
+            "cmrs_padded_spmv",
             "cmrs_calib_stream_read", "cmrs_calib_gather", "cmrs_features", "cmrs_mlp_forward", "cmrs_mlp_backward",
             "cmrs_mse_grad", "cmrs_adam_step", "cmrs_status_string", "cmrs_last_error"]
 
@@ -408,6 +418,58 @@ def spmm_batched(plan: SpmmPlan, stream=None) -> None:
     """Run a batch plan: one persistent launch."""
     st = lib.cmrs_spmm_batched(ctypes.byref(plan.plan), _stream(stream))
     _check(st, "cmrs_spmm_batched")
+
+
+def padded_bits(height: int) -> int:
+    return int(lib.cmrs_padded_bits(height))
+
+
+def padded_from_csr(row_ptr: torch.Tensor, col_ind: torch.Tensor, val: torch.Tensor, cols: int, height: int,
+                    stream=None) -> CmrsMatrix:
+    """CSR -> the padded CMRS of Sec. 6.7 (chunks of 64, <= 8 entries of a
+    row per chunk).  Synchronises the stream once (to size the output);
+    the result's nnz is the padded size, ``real_nnz`` the CSR's."""
+    _dev(row_ptr, "row_ptr", torch.int32)
+    _dev(col_ind, "col_ind", torch.int32)
+    _dev(val, "val")
+    if val.dtype not in _DT:
+        raise TypeError(f"unsupported value dtype {val.dtype}")
+    rows = row_ptr.numel() - 1
+    nnz = col_ind.numel()
+    strips = num_strips(rows, height)
+    if strips < 0 or padded_bits(height) < 0:
+        raise ValueError(f"bad height {height}")
+    dev = row_ptr.device
+    sp = torch.empty(strips + 1, dtype=torch.int32, device=dev)
+    wsb = int(lib.cmrs_padded_plan_workspace(rows, height))
+    ws = torch.empty(max(wsb, 8), dtype=torch.uint8, device=dev)
+    total = ctypes.c_int64(0)
+    st = lib.cmrs_padded_plan(rows, nnz, _ptr(row_ptr), height, _ptr(sp), ctypes.byref(total), ws.data_ptr(), wsb,
+                              _stream(stream))
+    _check(st, "cmrs_padded_plan")
+    pn = int(total.value)
+    cw = torch.empty(pn, dtype=torch.int32, device=dev)
+    vo = torch.empty(pn, dtype=val.dtype, device=dev)
+    st = lib.cmrs_padded_from_csr(rows, cols, nnz, _ptr(row_ptr), _ptr(col_ind), _ptr(val), _DT[val.dtype], height,
+                                  _ptr(sp), pn, _ptr(cw), _ptr(vo), _stream(stream))
+    _check(st, "cmrs_padded_from_csr")
+    M = CmrsMatrix(rows, cols, height, padded_bits(height), False, sp, cw, vo)
+    M.real_nnz = nnz
+    return M
+
+
+def padded_spmv(A: CmrsMatrix, x: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """y = A x for a matrix from padded_from_csr."""
+    xdt = torch.float64 if A.val.dtype == torch.float64 else torch.float32
+    _dev(x, "x", xdt)
+    if x.numel() != A.cols:
+        raise ValueError(f"x has {x.numel()} entries, the matrix {A.cols} columns")
+    y = out if out is not None else torch.empty(A.rows, dtype=xdt, device=x.device)
+    _dev(y, "y", xdt)
+    d = A.desc()
+    st = lib.cmrs_padded_spmv(ctypes.byref(d), _ptr(x), _ptr(y), _DT[xdt], _stream(stream))
+    _check(st, "cmrs_padded_spmv")
+    return y
 
 
 def validate_csr(row_ptr: torch.Tensor, col_ind: torch.Tensor, cols: int, stream=None) -> int:

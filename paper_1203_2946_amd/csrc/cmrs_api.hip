@@ -1,5 +1,6 @@
 // Host side of the C ABI declared in include/cmrs.h: argument validation,
 // error reporting and dispatch to the kernels.  Nothing here allocates.
+#include <limits.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -380,6 +381,90 @@ cmrs_status_t cmrs_spmm_batched(const cmrs_spmm_plan_t* plan, hipStream_t stream
             static_cast<size_t>(plan->waves / plan->grid) * plan->max_slots * 64 * (plan->val_dtype == CMRS_R64F ? 8 : 4))
         return fail(CMRS_ERR_INVALID_VALUE, "corrupt plan");
     return from_hip(cmrs::launch_spmm_batched(plan, stream), "cmrs_spmm_batched");
+}
+
+int32_t cmrs_padded_bits(int32_t height) {
+    if (height < 1 || height > CMRS_MAX_HEIGHT) return -1;
+    int32_t b = 0;
+    while ((1 << b) < height + 1) ++b;
+    return b < 4 ? 4 : b;
+}
+
+size_t cmrs_padded_plan_workspace(int32_t rows, int32_t height) {
+    if (rows < 0 || height < 1 || height > CMRS_MAX_HEIGHT) return 0;
+    return cmrs::padded_workspace_layout(cmrs_num_strips(rows, height)).total;
+}
+
+cmrs_status_t cmrs_padded_plan(int32_t rows, int32_t nnz, const int32_t* row_ptr, int32_t height,
+                               int32_t* strip_ptr_out, int64_t* padded_nnz_out, void* workspace,
+                               size_t workspace_bytes, hipStream_t stream) {
+    g_last_error[0] = 0;
+    if (rows < 0 || nnz < 0) return fail(CMRS_ERR_INVALID_VALUE, "negative size");
+    if (height < 1 || height > CMRS_MAX_HEIGHT)
+        return fail(CMRS_ERR_INVALID_VALUE, "height %d outside [1, %d]", height, CMRS_MAX_HEIGHT);
+    if (!row_ptr || !strip_ptr_out || !padded_nnz_out) return fail(CMRS_ERR_INVALID_VALUE, "NULL pointer");
+    const size_t need = cmrs_padded_plan_workspace(rows, height);
+    if (!workspace || workspace_bytes < need)
+        return fail(CMRS_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, workspace_bytes);
+    if (reinterpret_cast<uintptr_t>(workspace) & 7u) return fail(CMRS_ERR_INVALID_VALUE, "workspace not 8-byte aligned");
+    const int strips = cmrs_num_strips(rows, height);
+    cmrs_status_t st = from_hip(cmrs::launch_padded_count(rows, height, row_ptr, workspace, stream), "cmrs_padded_plan");
+    if (st != CMRS_OK) return st;
+    long long chunks = 0;
+    st = from_hip(hipMemcpyAsync(&chunks, cmrs::padded_total_ptr(strips, workspace), sizeof(chunks),
+                                 hipMemcpyDeviceToHost, stream),
+                  "cmrs_padded_plan");
+    if (st == CMRS_OK) st = from_hip(hipStreamSynchronize(stream), "cmrs_padded_plan");
+    if (st != CMRS_OK) return st;
+    const long long padded = chunks * 64;
+    *padded_nnz_out = padded;
+    if (padded > INT32_MAX)
+        return fail(CMRS_ERR_INDEX_OVERFLOW, "padded matrix would hold %lld entries (int32 offsets)", padded);
+    return from_hip(cmrs::launch_padded_strip_ptr(strips, workspace, strip_ptr_out, stream), "cmrs_padded_plan");
+}
+
+cmrs_status_t cmrs_padded_from_csr(int32_t rows, int32_t cols, int32_t nnz, const int32_t* row_ptr,
+                                   const int32_t* col_ind, const void* val_in, cmrs_dtype_t dtype, int32_t height,
+                                   const int32_t* strip_ptr, int32_t padded_nnz, uint32_t* col_word_out,
+                                   void* val_out, hipStream_t stream) {
+    g_last_error[0] = 0;
+    if (rows < 0 || cols < 0 || nnz < 0 || padded_nnz < 0) return fail(CMRS_ERR_INVALID_VALUE, "negative size");
+    if (height < 1 || height > CMRS_MAX_HEIGHT)
+        return fail(CMRS_ERR_INVALID_VALUE, "height %d outside [1, %d]", height, CMRS_MAX_HEIGHT);
+    if (!valid_dtype(dtype)) return fail(CMRS_ERR_INVALID_VALUE, "unknown dtype %d", (int)dtype);
+    if (padded_nnz < nnz || padded_nnz % 64) return fail(CMRS_ERR_INVALID_VALUE, "padded_nnz %d is not a plan's size", padded_nnz);
+    const int32_t bits = cmrs_padded_bits(height);
+    if (!cols_fit(cols, bits)) return fail(CMRS_ERR_INDEX_OVERFLOW, "cols=%d does not fit %d column bits", cols, 32 - bits);
+    if (!row_ptr || !strip_ptr) return fail(CMRS_ERR_INVALID_VALUE, "row_ptr or strip_ptr is NULL");
+    if (padded_nnz > 0 && (!col_ind || !val_in || !col_word_out || !val_out))
+        return fail(CMRS_ERR_INVALID_VALUE, "an entry array is NULL");
+    const size_t es = cmrs::dtype_bytes(dtype);
+    const size_t pz = static_cast<size_t>(padded_nnz), nz = static_cast<size_t>(nnz);
+    if (ranges_overlap(col_word_out, 4 * pz, col_ind, 4 * nz) || ranges_overlap(val_out, es * pz, val_in, es * nz) ||
+        ranges_overlap(col_word_out, 4 * pz, val_in, es * nz) || ranges_overlap(val_out, es * pz, col_ind, 4 * nz) ||
+        ranges_overlap(col_word_out, 4 * pz, val_out, es * pz))
+        return fail(CMRS_ERR_INVALID_VALUE, "outputs overlap inputs or each other");
+    if (rows == 0 || padded_nnz == 0) return CMRS_OK;
+    return from_hip(cmrs::launch_padded_fill(rows, height, bits, row_ptr, col_ind, val_in, dtype, strip_ptr,
+                                             col_word_out, val_out, stream),
+                    "cmrs_padded_from_csr");
+}
+
+cmrs_status_t cmrs_padded_spmv(const cmrs_mat_t* A, const void* x, void* y, cmrs_dtype_t xy_dtype,
+                               hipStream_t stream) {
+    g_last_error[0] = 0;
+    if (!A) return fail(CMRS_ERR_INVALID_VALUE, "matrix descriptor is NULL");
+    if (A->height < 1 || A->height > CMRS_MAX_HEIGHT || A->bits != cmrs_padded_bits(A->height))
+        return fail(CMRS_ERR_INVALID_VALUE, "height %d / bits %d are not a padded matrix's", A->height, A->bits);
+    cmrs_mat_t plain = *A;
+    plain.bits = cmrs_bits_for_height(A->height);
+    if (!cols_fit(A->cols, A->bits))
+        return fail(CMRS_ERR_INDEX_OVERFLOW, "cols=%d does not fit %d column bits", A->cols, 32 - A->bits);
+    if (A->nnz % 64) return fail(CMRS_ERR_INVALID_VALUE, "nnz %d of a padded matrix is not a multiple of 64", A->nnz);
+    if (A->nnz > 0 && A->cols < 1) return fail(CMRS_ERR_INVALID_VALUE, "entries but no columns");
+    cmrs_status_t st = check_spmv_args(&plain, x, y, xy_dtype, CMRS_SPMV_AUTO);
+    if (st != CMRS_OK || A->rows == 0) return st;
+    return from_hip(cmrs::launch_padded_spmv(A, x, y, stream), "cmrs_padded_spmv");
 }
 
 cmrs_status_t cmrs_validate_csr(int32_t rows, int32_t cols, int32_t nnz, const int32_t* row_ptr,

@@ -123,6 +123,21 @@ hipError_t build_spmm_plan(int count, const cmrs_mat_t* mats, const int* nrhs, c
                            int blocks_per_cu, void* desc, cmrs_spmm_plan_t* plan, hipStream_t stream);
 hipError_t launch_spmm_batched(const cmrs_spmm_plan_t* plan, hipStream_t stream);
 
+// Modified CMRS of Sec. 6.7 (padded strips): conversion workspace, int64
+// chunk counts, their prefix sums and the scan's block totals.
+struct PaddedWorkspaceLayout {
+    int nb;
+    size_t chunks_off, prefix_off, bsum_off, total;
+};
+PaddedWorkspaceLayout padded_workspace_layout(int strips);
+hipError_t launch_padded_count(int rows, int height, const int* row_ptr, void* workspace, hipStream_t stream);
+const long long* padded_total_ptr(int strips, const void* workspace);
+hipError_t launch_padded_strip_ptr(int strips, const void* workspace, int32_t* strip_ptr, hipStream_t stream);
+hipError_t launch_padded_fill(int rows, int height, int bits, const int* row_ptr, const int* col_ind,
+                              const void* val_in, cmrs_dtype_t dtype, const int* strip_ptr, uint32_t* word_out,
+                              void* val_out, hipStream_t stream);
+hipError_t launch_padded_spmv(const cmrs_mat_t* A, const void* x, void* y, hipStream_t stream);
+
 hipError_t launch_validate_csr(int32_t rows, int32_t cols, int32_t nnz, const int32_t* row_ptr,
                                const int32_t* col_ind, int32_t* flag, hipStream_t stream);
 
