@@ -57,6 +57,8 @@ def parse():
     p.add_argument("--no-sweep", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--rows", type=int, default=1 << 20)
+    p.add_argument("--no-extras", action="store_true",
+                   help="skip the selector, batched, precision and padded reports")
     return p.parse_args()
 
 
@@ -82,6 +84,192 @@ def read_traffic(kernel_tag: str):
         if f.get("tag") == kernel_tag and f.get("src") == src:
             return int(f["fetch_bytes"]) + int(f["write_bytes"])
     return None
+
+
+# -------------------------------------------------------------------- extra reports
+def _median_ms(fn, reps=10, warmup=2):
+    import torch
+    for _ in range(warmup):
+        fn()
+    evs = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        evs.append((a, b))
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in evs]))
+
+
+def selector_report(rp, ci, v64, cols):
+    """Learned (height, schedule) choice against exhaustive search over the 24
+    classes: on this workload, on 100 fresh seeded matrices of the training
+    families, and on the held-out part of the committed timing set."""
+    import torch
+    from paper_1203_2946_amd import selector as S
+    model = S.load()
+    d = np.load(S.DATA_PATH, allow_pickle=False)
+    w = np.load(S.WEIGHTS_PATH, allow_pickle=False)
+    n_train = int(w["n_train"])
+    te = np.arange(n_train, d["features"].shape[0])
+    pred = model.predict(torch.from_numpy(d["features"][te]).cuda()).cpu().numpy()
+    t = d["times_ms"][te]
+    held = {"matrices": int(te.size), "regret": round(S.regret(t, pred.argmin(1)), 4),
+            "regret_default_h8_group": round(S.regret(t, np.full(te.size, S.DEFAULT_CLASS)), 4),
+            "regret_best_fixed": round(min(S.regret(t, np.full(te.size, c)) for c in range(S.N_CLASSES)), 4)}
+    # This workload.
+    feat = S.features(rp, ci, cols)
+    c_pred = int(model.predict(feat.reshape(1, -1)).argmin().item())
+    run = S.ClassRunner(rp, ci, v64, cols)
+    tw = run.time_classes(reps=7)
+    c_best = int(np.nanargmin(tw))
+    here = {"predicted": "h%d_%s" % S.CLASSES[c_pred], "exhaustive_best": "h%d_%s" % S.CLASSES[c_best],
+            "predicted_ms": round(float(tw[c_pred]), 5), "best_ms": round(float(tw[c_best]), 5),
+            "tune_ratio": round(float(tw[c_best] / tw[c_pred]), 4)}
+    del run
+    # Fresh matrices (generator seed 1; the timing set used seed 0).
+    dev = torch.device("cuda:0")
+    live_t, live_c = [], []
+    for i in range(100):
+        fam, mrp, mci, mval, mcols = S.sample_matrix(i, 1, dev, max_nnz=20_000_000)
+        f = S.features(mrp, mci, mcols)
+        live_c.append(int(model.predict(f.reshape(1, -1)).argmin().item()))
+        r = S.ClassRunner(mrp, mci, mval, mcols)
+        live_t.append(r.time_classes(reps=5))
+        del r, mrp, mci, mval
+    live_t = np.array(live_t)
+    live_c = np.array(live_c)
+    live = {"matrices": 100, "regret": round(S.regret(live_t, live_c), 4),
+            "tune_ratio_geomean": round(1.0 / (1.0 + S.regret(live_t, live_c)), 4),
+            "regret_default_h8_group": round(S.regret(live_t, np.full(100, S.DEFAULT_CLASS)), 4)}
+    log(f"selector: this workload {here['predicted']} vs best {here['exhaustive_best']} ratio {here['tune_ratio']}; "
+        f"fresh regret {live['regret']}; held-out regret {held['regret']}")
+    return {"classes": "6 heights x (wave, wave_nt, group, colblock4)", "this_workload": here, "fresh": live,
+            "held_out": held}
+
+
+def batched_report():
+    """The uneven batch: 256 matrices (27-point stencils and band matrices,
+    10k-500k rows log-uniform, 1-8 right-hand sides), one persistent launch
+    replayed from a HIP graph against 256 separate cmrs_spmm launches."""
+    import torch
+    from paper_1203_2946_amd import cmrs, batched as B
+    from synth import gpu_families as F
+    W = F.batched_workload(seed=0)
+    rows = sum(rp.numel() - 1 for _, rp, _, _, _, _ in W)
+    nnz = sum(ci.numel() for _, _, ci, _, _, _ in W)
+    out = {"workload": "256 matrices, rows log-uniform 10k-500k, alternating 27-point stencils and band matrices "
+                       "(bandwidth 8-64, 60% fill), N(0,1) values, 1-8 right-hand sides, seed 0",
+           "rows": rows, "nnz": nnz, "rhs_total": sum(r for *_, r in W)}
+    for dt, tdt in (("f64", torch.float64), ("f32", torch.float32)):
+        best = None
+        for h in (2, 4):
+            mats, Xs, Ys, nr = [], [], [], []
+            for fam, rp, ci, val, cols, r in W:
+                mats.append(cmrs.from_csr(rp, ci, val.to(tdt), cols, h, sort=True))
+                nr.append(r)
+                Xs.append(torch.randn(cols, r, dtype=tdt, device="cuda"))
+                Ys.append(torch.empty(rp.numel() - 1, r, dtype=tdt, device="cuda"))
+            plan, tun, table = B.tune(mats, Xs, Ys, reps=5)
+            g = B.Graph(plan)
+            tg = _median_ms(g.replay)
+            if best is None or tg < best[0]:
+                ts = _median_ms(lambda: B.run_separate(mats, Xs, Ys))
+                g.replay()
+                torch.cuda.synchronize()
+                Yg = [y.clone() for y in Ys]
+                B.run_separate(mats, Xs, Ys)
+                torch.cuda.synchronize()
+                dev_max = max(float(((a - b).abs().max() / (b.abs().max() + 1e-300)).item()) for a, b in zip(Yg, Ys))
+                best = (tg, ts, h, tun, B.batch_bytes(mats, nr), B.batch_flops(mats, nr), plan.tiles, plan.grid,
+                        dev_max)
+            del mats, Xs, Ys, plan, g
+            torch.cuda.empty_cache()
+        tg, ts, h, tun, byt, flo, tiles, grid, dev_max = best
+        out[dt] = {"height": h, "tuning": tun, "tiles": tiles, "workgroups": grid,
+                   "graph_persistent_ms": round(tg, 4), "separate_launches_ms": round(ts, 4),
+                   "speedup_vs_separate": round(ts / tg, 3), "alg_bytes": byt,
+                   "gbs": round(byt / tg / 1e6, 1), "frac_of_hbm_peak": round(byt / tg / 1e6 / HBM_PEAK_GBS, 4),
+                   "gflops": round(flo / tg / 1e6, 1),
+                   "max_rel_diff_vs_separate": dev_max}
+        log(f"batched {dt}: h={h} graph {tg:.3f} ms ({byt / tg / 1e6:.0f} GB/s) vs separate {ts:.3f} ms")
+    return out
+
+
+def precision_report():
+    """The skewed-row workload in fp64, fp32 and bf16-value/fp32-accumulate:
+    SpMV throughput and componentwise error against the fp64 oracle."""
+    import torch
+    import oracle
+    import synth
+    from paper_1203_2946_amd import cmrs, model
+    A = synth.zipf_clustered(2_000_000, seed=0)
+    x64 = synth.uniform_vector(A.cols, seed=1)
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(A.row_ptr).to(dev)
+    ci = torch.from_numpy(A.col_ind).to(dev)
+    yref = oracle.csr_spmv(A.row_ptr, A.col_ind, A.val, x64)
+    absmv = oracle.csr_absmv(A.row_ptr, A.col_ind, A.val, x64)
+    k = np.diff(A.row_ptr).astype(np.float64)
+    out = {"workload": f"zipf n={A.rows} (Zipf(2.0) row lengths clipped to [1,10000], 70% of columns within "
+                       f"+-512 of the diagonal, U[-1,1] values and x, seed 0)", "rows": A.rows, "nnz": A.nnz}
+    for dt in ("f64", "f32", "bf16"):
+        if dt == "f64":
+            v = torch.from_numpy(A.val).to(dev)
+            x = torch.from_numpy(x64).to(dev)
+            sv, sx, u, rep = 8, 8, 2.0 ** -53, 0.0
+        else:
+            v = torch.from_numpy(A.val).to(dev).to(torch.float32 if dt == "f32" else torch.bfloat16)
+            x = torch.from_numpy(x64).to(dev).float()
+            sv, sx, u, rep = (4 if dt == "f32" else 2), 4, 2.0 ** -24, (0.0 if dt == "f32" else 2.0 ** -8)
+        best = None
+        for h in (4, 8, 16):
+            M = cmrs.from_csr(rp, ci, v, A.cols, h, sort=True)
+            tm = _median_ms(lambda: cmrs.spmv(M, x))
+            if best is None or tm < best[0]:
+                y = cmrs.spmv(M, x).cpu().numpy().astype(np.float64)
+                best = (tm, h, y, M.strips)
+            del M
+        tm, h, y, strips = best
+        bp = model.beta_plus(A.nnz, A.rows, A.cols, strips, sv, sx, sx)
+        err = np.abs(y - yref)
+        # Bound of the path: fp64 4 k u |A||x|; fp32 / bf16 values with fp32 x: rounding of the stored value
+        # (bf16: 2^-8) and of x (2^-24) plus fp32 accumulation.
+        bound = 4 * k * u * absmv if dt == "f64" else 2.0 * (rep + (k + 2) * u) * absmv
+        nz = absmv > 0
+        out[dt] = {"height": h, "spmv_warm_ms": round(tm, 5), "gbs_plus": round(bp / tm / 1e6, 1),
+                   "frac_of_hbm_peak": round(bp / tm / 1e6 / HBM_PEAK_GBS, 4),
+                   "max_err_over_bound": float((err[nz] / bound[nz]).max()) if nz.any() else 0.0,
+                   "rows_over_bound": int((err > bound).sum()),
+                   "max_componentwise_rel_err": float((err[nz] / absmv[nz]).max()) if nz.any() else 0.0}
+        log(f"precision {dt}: h={h} {tm * 1e3:.1f} us ({bp / tm / 1e6:.0f} GB/s), max err/bound "
+            f"{out[dt]['max_err_over_bound']:.3g}")
+    return out
+
+
+def padded_report(rp, ci, v64, x, cols, nnz, best_plain_ms):
+    """Modified CMRS of Sec. 6.7 on this workload: memory overhead of the
+    padding, conversion and SpMV times against the best plain SpMV."""
+    import torch
+    from paper_1203_2946_amd import cmrs, model
+    out = {}
+    for h in (8, 16, 32):
+        t0 = time.perf_counter()
+        M = cmrs.padded_from_csr(rp, ci, v64, cols, h)
+        torch.cuda.synchronize()
+        conv_ms = (time.perf_counter() - t0) * 1e3
+        tm = _median_ms(lambda: cmrs.padded_spmv(M, x))
+        rows = rp.numel() - 1
+        bp = model.beta_plus(nnz, rows, cols, M.strips, 8, 8, 8)
+        stored = (8 + 4) * M.nnz + 4 * (M.strips + 1) + 8 * cols + 8 * rows
+        out[f"h{h}"] = {"padded_nnz": M.nnz, "memory_overhead": round(M.nnz / nnz - 1, 4),
+                        "convert_wall_ms": round(conv_ms, 3), "spmv_warm_ms": round(tm, 5),
+                        "gbs_plus": round(bp / tm / 1e6, 1), "gbs_stored": round(stored / tm / 1e6, 1),
+                        "speedup_vs_best_plain": round(best_plain_ms / tm, 3)}
+        log(f"padded h={h}: overhead {M.nnz / nnz - 1:.3f}, spmv {tm * 1e3:.1f} us vs plain {best_plain_ms * 1e3:.1f}")
+        del M
+    return out
 
 
 def main():
@@ -322,6 +510,15 @@ def main():
                "ms_per_step": round(tc * 1e3, 1)}
         log(f"cpu oracle: {tc:.2f} s/step -> {cpu['value']} GB/s")
 
+    extras = {}
+    if not args.no_extras:
+        warm_plain = [r["spmv_warm_ms"] for r in sweep if r["dtype"] == "f64"]
+        best_plain = min(warm_plain) if warm_plain else protocol(P.spmv, cold=False)[0]
+        extras["padded"] = padded_report(rp, ci, v64, x_d["f64"], A.cols, A.nnz, best_plain)
+        extras["selector"] = selector_report(rp, ci, v64, A.cols)
+        extras["precision"] = precision_report()
+        extras["batched"] = batched_report()
+
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True, "scaling": "weak",
@@ -331,7 +528,7 @@ def main():
                    "schedule": sched, "sorted": True,
                    "step": " + ".join(names), "alg_bytes_per_step": b_step},
         "roofline": roofline, "cpu_baseline": cpu, "spmv": spmv, "ceiling": ceiling, "kernels": kern,
-        "kernel_src": kernel_source_hash(), "sweep": sweep,
+        "kernel_src": kernel_source_hash(), **extras, "sweep": sweep,
     }
     print(json.dumps(out), flush=True)
 
