@@ -63,8 +63,8 @@ __device__ inline void spmm_pass(const SpmmMat& m, int sb, int s_end, AT* __rest
         const size_t ldx = static_cast<size_t>(m.ldx);
         for (int base = lo + e; base < hi; base += U * G) {
             // Out-of-range entries are clamped to the last one of the strip
-            // (a valid address) and their products dropped, so every load
-            // of the step is issued without a branch.
+            // (a valid address), so the stream loads of the step issue
+            // without a branch; their gathers are masked off.
             uint32_t w[U];
             VT v[U];
             XT xv[U][RB];
@@ -76,9 +76,11 @@ __device__ inline void spmm_pass(const SpmmMat& m, int sb, int s_end, AT* __rest
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const XT* xr = x + static_cast<size_t>(w[u] >> bits) * ldx;
+                if (base + u * G < hi) {
+                    const XT* xr = x + static_cast<size_t>(w[u] >> bits) * ldx;
 #pragma unroll
-                for (int k = 0; k < RB; ++k) xv[u][k] = xr[k < nrhs ? k : 0];
+                    for (int k = 0; k < RB; ++k) xv[u][k] = xr[k < nrhs ? k : 0];
+                }
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {

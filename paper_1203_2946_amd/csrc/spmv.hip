@@ -134,8 +134,8 @@ __device__ inline void accumulate_run(Acc& acc, int lo, int hi, int bits, const 
     const uint32_t mask = (1u << bits) - 1u;
     for (int base = lo; base < hi; base += U * kWave) {
         // Entries past the run are clamped to its last entry (a valid
-        // address) and their products dropped: every load of the step is
-        // issued without a branch.
+        // address) so the stream loads of the step issue without a branch;
+        // their gathers are masked off and their products dropped.
         uint32_t w[U];
         VT v[U];
         XT xv[U];
@@ -146,7 +146,8 @@ __device__ inline void accumulate_run(Acc& acc, int lo, int hi, int bits, const 
             v[u] = stream_load<NT>(val + j);
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) xv[u] = x[w[u] >> bits];
+        for (int u = 0; u < U; ++u)
+            if (base + u * kWave + lane < hi) xv[u] = x[w[u] >> bits];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (base + u * kWave + lane < hi) {
@@ -264,7 +265,8 @@ __device__ inline void group_runs(int lo, int hi, int long_len, int bits, const 
                 v[u] = stream_load<NT>(val + j);
             }
 #pragma unroll
-            for (int u = 0; u < U; ++u) xv[u] = x[w[u] >> bits];
+            for (int u = 0; u < U; ++u)
+                if (j0 + u * G < hi) xv[u] = x[w[u] >> bits];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int j = j0 + u * G;
