@@ -59,6 +59,12 @@ def parse():
     p.add_argument("--rows", type=int, default=1 << 20)
     p.add_argument("--no-extras", action="store_true",
                    help="skip the selector, batched, precision and padded reports")
+    p.add_argument("--only", choices=["batched", "precision"], default=None,
+                   help="run only that report (for profiling) and print it as one JSON line")
+    p.add_argument("--batched-fixed", default=None,
+                   help="skip the batched autotuner: dtype=height:tile_nnz:group:blocks_per_cu[,dtype=...]")
+    p.add_argument("--copy-calib", action="store_true",
+                   help="only run three plain 1 GiB device-to-device copies (calibrates HBM byte counters)")
     return p.parse_args()
 
 
@@ -149,7 +155,7 @@ def selector_report(rp, ci, v64, cols):
             "held_out": held}
 
 
-def batched_report():
+def batched_report(fixed=None):
     """The uneven batch: 256 matrices (27-point stencils and band matrices,
     10k-500k rows log-uniform, 1-8 right-hand sides), one persistent launch
     replayed from a HIP graph against 256 separate cmrs_spmm launches."""
@@ -162,16 +168,26 @@ def batched_report():
     out = {"workload": "256 matrices, rows log-uniform 10k-500k, alternating 27-point stencils and band matrices "
                        "(bandwidth 8-64, 60% fill), N(0,1) values, 1-8 right-hand sides, seed 0",
            "rows": rows, "nnz": nnz, "rhs_total": sum(r for *_, r in W)}
+    fixed_cfg = {}
+    if fixed:
+        for item in fixed.split(","):
+            k, v = item.split("=")
+            h_, t_, g_, b_ = (int(z) for z in v.split(":"))
+            fixed_cfg[k] = (h_, {"tile_nnz": t_, "group": g_, "blocks_per_cu": b_})
     for dt, tdt in (("f64", torch.float64), ("f32", torch.float32)):
         best = None
-        for h in (2, 4):
+        for h in ((fixed_cfg[dt][0],) if dt in fixed_cfg else (2, 4)):
             mats, Xs, Ys, nr = [], [], [], []
             for fam, rp, ci, val, cols, r in W:
                 mats.append(cmrs.from_csr(rp, ci, val.to(tdt), cols, h, sort=True))
                 nr.append(r)
                 Xs.append(torch.randn(cols, r, dtype=tdt, device="cuda"))
                 Ys.append(torch.empty(rp.numel() - 1, r, dtype=tdt, device="cuda"))
-            plan, tun, table = B.tune(mats, Xs, Ys, reps=5)
+            if dt in fixed_cfg:
+                tun = fixed_cfg[dt][1]
+                plan = cmrs.spmm_plan(mats, Xs, Ys, **tun)
+            else:
+                plan, tun, table = B.tune(mats, Xs, Ys, reps=5)
             g = B.Graph(plan)
             tg = _median_ms(g.replay)
             if best is None or tg < best[0]:
@@ -287,6 +303,18 @@ def main():
     from paper_1203_2946_amd import cmrs, model
 
     assert torch.cuda.is_available(), "needs a GPU"
+    if args.copy_calib:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": a.numel() * 4, "copies": 3}), flush=True)
+        return
+    if args.only:
+        rep = batched_report(args.batched_fixed) if args.only == "batched" else precision_report()
+        print(json.dumps({args.only: rep}), flush=True)
+        return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     props = torch.cuda.get_device_properties(dev)

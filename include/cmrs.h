@@ -244,10 +244,11 @@ cmrs_status_t cmrs_spmm(const cmrs_mat_t *A, int32_t nrhs, const void *X, int32_
  * the caller's device buffer `desc` (cmrs_spmm_plan_bytes() bytes), a small
  * queue header, one descriptor per matrix (its arrays, X_i, Y_i, nrhs_i,
  * ldx_i, ldy_i) and the tile list.  cmrs_spmm_batched() then launches
- * plan->grid workgroups that take tiles from the queue until it is empty;
- * the last wave to finish resets the queue, so the same plan can be
- * launched again, one launch at a time per plan, and captured into a HIP
- * graph.  Tile t of matrix i is computed exactly as cmrs_spmm computes those
+ * plan->grid workgroups that take tiles from the queues until they are
+ * empty: one queue per XCD over a contiguous eighth of the tile list, drained
+ * first by that XCD's workgroups; the last wave to finish resets the queues,
+ * so the same plan can be launched again, one launch at a time per plan, and
+ * captured into a HIP graph.  Tile t of matrix i is computed exactly as cmrs_spmm computes those
  * strips with the plan's group width.
  *
  * cmrs_spmm_plan is set-up, not hot path: it copies the descriptor image

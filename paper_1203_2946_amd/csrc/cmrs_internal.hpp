@@ -108,7 +108,7 @@ struct SpmmPlanShape {
     int max_slots;  // largest next_pow2(height) * next_pow2(nrhs) of the batch
     size_t bytes;
 };
-constexpr size_t kSpmmHeaderBytes = 256;
+constexpr size_t kSpmmHeaderBytes = 1024;  // 8 per-XCD queue counters + done counter, 64 B apart
 
 size_t spmm_wave_lds_bytes(int slots, size_t acc_bytes);
 int spmm_waves_per_block(size_t wave_bytes);

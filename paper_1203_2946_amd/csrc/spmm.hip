@@ -12,9 +12,10 @@
 // spreads the reads of one instruction over distinct banks too.
 //
 // The batched path runs that body from one persistent kernel: waves take
-// work tiles (a matrix and a range of its strips) from a queue counter in the
-// plan until the queue is empty; the last wave out resets the counter, so
-// the same plan can be launched again and replayed from a HIP graph.  A grid
+// work tiles (a matrix and a range of its strips) from per-XCD queue counters
+// in the plan until every queue is empty; the last wave out resets the
+// counters, so the same plan can be launched again and replayed from a HIP
+// graph.  A grid
 // stride over strip passes (the listing's loop over strips in the paper's
 // appendix) is the special case of one tile per wave.
 #include <string.h>
@@ -147,9 +148,14 @@ __device__ inline void spmm_tile_rb(const SpmmMat& m, int s0, int s1, AT* buf, i
     }
 }
 
-// queue[0]: next tile; queue[kQueueDone]: waves finished.  Both are zero at
-// launch and are zero again when the last wave leaves.
-constexpr int kQueueDone = 16;
+// Work queues, one per XCD: queue x hands out the tiles [x*n/8, (x+1)*n/8)
+// through the counter queue[x * 16] (one 64-byte line each).  Workgroup b
+// runs on XCD b mod 8 and drains that XCD's queue first, so neighbouring
+// tiles (and the parts of X they gather) stay in one L2; then it takes tiles
+// left in the other queues.  queue[kQueueDone] counts finished waves.  All
+// counters are zero at launch and again when the last wave leaves.
+constexpr int kQueueStride = 16;
+constexpr int kQueueDone = kNumXcd * kQueueStride;
 
 template <typename VT, typename XT, typename AT>
 __global__ __launch_bounds__(kSpmmMaxWaves * kWave) void spmm_persistent_kernel(
@@ -159,29 +165,40 @@ __global__ __launch_bounds__(kSpmmMaxWaves * kWave) void spmm_persistent_kernel(
     const int lane = lane_id();
     const int wave = uniform(static_cast<int>(threadIdx.x) / kWave);
     AT* buf = reinterpret_cast<AT*>(spmm_lds) + static_cast<size_t>(wave) * wave_slots;
-    for (;;) {
-        unsigned t = 0;
-        if (lane == 0) t = __hip_atomic_fetch_add(&queue[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        t = static_cast<unsigned>(uniform(static_cast<int>(__shfl(t, 0))));
-        if (t >= static_cast<unsigned>(ntiles)) break;
-        const SpmmTile tile = tiles[t];
-        const SpmmMat m = mats[tile.mat];
-        switch (m.hb) {
-            case 1: spmm_tile_rb<1, VT, XT, AT>(m, tile.s0, tile.s1, buf, lane); break;
-            case 2: spmm_tile_rb<2, VT, XT, AT>(m, tile.s0, tile.s1, buf, lane); break;
-            case 4: spmm_tile_rb<4, VT, XT, AT>(m, tile.s0, tile.s1, buf, lane); break;
-            case 8: spmm_tile_rb<8, VT, XT, AT>(m, tile.s0, tile.s1, buf, lane); break;
-            case 16: spmm_tile_rb<16, VT, XT, AT>(m, tile.s0, tile.s1, buf, lane); break;
-            default: spmm_tile_rb<32, VT, XT, AT>(m, tile.s0, tile.s1, buf, lane); break;
+    const int home = static_cast<int>(blockIdx.x) % kNumXcd;
+    for (int a = 0; a < kNumXcd; ++a) {
+        const int qx = (home + a) % kNumXcd;
+        const long long lo = static_cast<long long>(qx) * ntiles / kNumXcd;
+        const long long hi = static_cast<long long>(qx + 1) * ntiles / kNumXcd;
+        for (;;) {
+            unsigned c = 0;
+            if (lane == 0)
+                c = __hip_atomic_fetch_add(&queue[qx * kQueueStride], 1u, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+            c = static_cast<unsigned>(uniform(static_cast<int>(__shfl(c, 0))));
+            const long long t = lo + c;
+            if (t >= hi) break;
+            const SpmmTile tile = tiles[t];
+            const SpmmMat m = mats[tile.mat];
+            switch (m.hb) {
+                case 1: spmm_tile_rb<1, VT, XT, AT>(m, tile.s0, tile.s1, buf, lane); break;
+                case 2: spmm_tile_rb<2, VT, XT, AT>(m, tile.s0, tile.s1, buf, lane); break;
+                case 4: spmm_tile_rb<4, VT, XT, AT>(m, tile.s0, tile.s1, buf, lane); break;
+                case 8: spmm_tile_rb<8, VT, XT, AT>(m, tile.s0, tile.s1, buf, lane); break;
+                case 16: spmm_tile_rb<16, VT, XT, AT>(m, tile.s0, tile.s1, buf, lane); break;
+                default: spmm_tile_rb<32, VT, XT, AT>(m, tile.s0, tile.s1, buf, lane); break;
+            }
         }
     }
-    // Every wave has taken its last ticket before it counts itself out, so
-    // the wave that counts last may reset the queue for the next launch.
+    // Every wave has taken its last ticket from every queue before it counts
+    // itself out, so the wave that counts last may reset them for the next
+    // launch.
     if (lane == 0) {
         const unsigned d =
             __hip_atomic_fetch_add(&queue[kQueueDone], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (d == static_cast<unsigned>(waves_total - 1)) {
-            __hip_atomic_store(&queue[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int x = 0; x < kNumXcd; ++x)
+                __hip_atomic_store(&queue[x * kQueueStride], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&queue[kQueueDone], 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
     }

@@ -159,14 +159,14 @@ def _batch(C, mats, nrhs):
 def test_spmm_plan_bytes_counts_tiles(C):
     # 1000 rows, height 4: 250 strips of 108 entries; one right-hand side
     # unrolls 8 entries per slot: 108 / 8 -> 16 slots, 4 strips per pass;
-    # 32768 / 108 -> 300 strips per tile: one tile.  Header 256 B, one 96 B
+    # 32768 / 108 -> 300 strips per tile: one tile.  Header 1024 B, one 96 B
     # descriptor, one 16 B tile.
     m, r = _batch(C, [_mat(C, rows=1000, cols=1000, nnz=27000, height=4)], [1])
-    assert C.lib.cmrs_spmm_plan_bytes(1, m, r, None) == 256 + 96 + 16
+    assert C.lib.cmrs_spmm_plan_bytes(1, m, r, None) == 1024 + 96 + 16
     tun = C.SpmmTuning(1000, 0, 0, 0)       # 1000 / 108 -> 9 -> 8 strips per tile: 32 tiles
-    assert C.lib.cmrs_spmm_plan_bytes(1, m, r, ctypes.byref(tun)) == 256 + 96 + 16 * 32
+    assert C.lib.cmrs_spmm_plan_bytes(1, m, r, ctypes.byref(tun)) == 1024 + 96 + 16 * 32
     m2, r2 = _batch(C, [_mat(C, rows=1000, cols=1000, nnz=27000, height=4), _mat(C, rows=0, nnz=0)], [1, 8])
-    assert C.lib.cmrs_spmm_plan_bytes(2, m2, r2, None) == 256 + 2 * 96 + 16
+    assert C.lib.cmrs_spmm_plan_bytes(2, m2, r2, None) == 1024 + 2 * 96 + 16
     bad = C.SpmmTuning(0, 0, 0, 1)           # reserved field set
     assert C.lib.cmrs_spmm_plan_bytes(1, m, r, ctypes.byref(bad)) == 0
     m3, r3 = _batch(C, [_mat(C)], [9])
