@@ -68,12 +68,16 @@ def parse():
     return p.parse_args()
 
 
+# Sources of the kernels a bench step runs (conversions, SpMV schedules and
+# their shared device helpers); counters taken from other sources are stale.
+STEP_SOURCES = ("convert.hip", "spmv.hip", "cmrs_device.hpp", "cmrs_internal.hpp")
+
+
 def kernel_source_hash() -> str:
     d = os.path.join(ROOT, "paper_1203_2946_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp")):
-            h.update(open(os.path.join(d, f), "rb").read())
+    for f in STEP_SOURCES:
+        h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 
 

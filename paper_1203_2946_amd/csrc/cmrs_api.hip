@@ -8,7 +8,7 @@
 #include <algorithm>
 #include <vector>
 
-#include "cmrs_internal.hpp"
+#include "cmrs_ext.hpp"
 
 namespace {
 

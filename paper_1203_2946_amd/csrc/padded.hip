@@ -24,7 +24,7 @@
 #include <limits.h>
 
 #include "cmrs_device.hpp"
-#include "cmrs_internal.hpp"
+#include "cmrs_ext.hpp"
 
 namespace cmrs {
 

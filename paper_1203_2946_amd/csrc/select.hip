@@ -21,7 +21,7 @@
 #include <math.h>
 
 #include "cmrs_device.hpp"
-#include "cmrs_internal.hpp"
+#include "cmrs_ext.hpp"
 
 namespace cmrs {
 
