@@ -226,3 +226,22 @@ def test_class_runner_matches_oracle():
             torch.cuda.synchronize()
             err = np.abs(run.y.cpu().numpy() - ref)
             assert np.all(err <= bound), (fam, S.CLASSES[c])
+
+
+def test_autotune_paths():
+    """autotune: exhaustive (no model) returns the fastest measured class;
+    top-k timing returns one of the model's k best predictions."""
+    S = _sel()
+    from synth import gpu_families as F
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(77)
+    rp, ci, val, cols = F.generate("poisson", 40_000, gen)
+    run = S.ClassRunner(rp, ci, val, cols)
+    c_ex = S.autotune(run, None, None)
+    assert 0 <= c_ex < S.N_CLASSES
+    model = S.Mlp(S.init_params(5, "cuda"))
+    feat = S.features(rp, ci, cols)
+    pred = model.predict(feat.reshape(1, -1)).cpu().numpy()[0]
+    c3 = S.autotune(run, feat, model, top_k=3)
+    assert c3 in set(np.argsort(pred)[:3].tolist())
+    assert S.autotune(run, feat, model, top_k=1) == int(np.argmin(pred))

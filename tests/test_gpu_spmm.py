@@ -285,3 +285,27 @@ def test_batched_full_workload_sampled_rows(C):
                 ref = oracle.csr_spmv(sub_rp, cols_i, vals_i, xk)[0]
                 tol = oracle.spmv_bound(sub_rp, cols_i, vals_i, xk, U64, factor=4.0)[0]
                 assert abs(Yh[i, k] - ref) <= tol, (i, k)
+
+
+def test_autotuner_and_graph_runner(C):
+    """batched.tune picks one of its candidate plans, whose results match the
+    oracle; a Graph of it replays the same bits."""
+    from paper_1203_2946_amd import batched as B
+    mats, Xs, Ys, host = _batch(C, seed=31, count=10)
+    plan, tun, table = B.tune(mats, Xs, Ys, candidates={"tile_nnz": (2000, 20000), "group": (0, 4),
+                                                        "blocks_per_cu": (1, 4)}, reps=2)
+    assert len(table) == 8 and tun in [t for t, _ in table]
+    assert min(ms for _, ms in table) == [ms for t, ms in table if t == tun][0]
+    g = B.Graph(plan)
+    for Y in Ys:
+        Y.fill_(float("nan"))
+    g.replay()
+    torch.cuda.synchronize()
+    first = [Y.cpu().numpy().copy() for Y in Ys]
+    for (A, hv, Xh), y in zip(host, first):
+        _check_cols(A, hv, "f64", Xh, y)
+    g.replay()
+    torch.cuda.synchronize()
+    for Y, y in zip(Ys, first):
+        assert np.array_equal(Y.cpu().numpy().view(np.uint64), y.view(np.uint64))
+    assert B.batch_bytes(mats, [X.shape[1] for X in Xs]) > 0

@@ -92,3 +92,12 @@ def test_laplace_counts():
     A = synth.laplace2d(64)
     assert A.rows == 4096 and A.nnz == 20224
     assert set(np.unique(A.val).tolist()) == {-1.0, 4.0}
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""
