@@ -262,6 +262,7 @@ __global__ __launch_bounds__(kConvThreads) void from_csr_group_kernel(
     constexpr int NG = kWave / G;
     constexpr int CAP = G * E;
     __shared__ uint64_t lds[SORT ? kConvWaves : 1][SORT ? 2 * kWave * E : 1];
+    __shared__ int rowtab[SORT ? kConvWaves : 1][SORT ? NG * (HB + 1) : 1];
     const int lane = lane_id();
     const int wave = uniform(static_cast<int>(threadIdx.x) / kWave);
     const int strip0 = (xcd_logical_block(blockIdx.x, gridDim.x) * kConvWaves + wave) * NG;
@@ -319,22 +320,40 @@ __global__ __launch_bounds__(kConvThreads) void from_csr_group_kernel(
         }
         return;
     } else {
-        // Rows must ascend (non-strictly) by column for the merge.
+        // Keys (word << 32 | position in strip) of every strip the group holds,
+        // and the strip-relative row pointers of rows 0..HB (rows past the
+        // strip: n), in LDS.
+        const bool fits = valid && !special;
+        uint64_t* A = &lds[wave][gbase * E];
+        uint64_t* B = &lds[wave][kWave * E + gbase * E];
+        int* rtab = &rowtab[wave][g * (HB + 1)];
+        uint64_t key[E];
+        int pos[E];
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            if (u >= umax) break;
+            const int p = q + G * u;
+            const uint32_t w = (static_cast<uint32_t>(c[u]) << bits) | static_cast<uint32_t>(t[u]);
+            key[u] = (static_cast<uint64_t>(w) << 32) | static_cast<uint32_t>(p);
+            pos[u] = p;
+            if (fits && p < n) A[p] = key[u];
+        }
+        if (q < HB) rtab[q] = q < nr ? myrp - s0 : n;
+        if (q == 0) rtab[HB] = n;
+        wave_lds_sync();
+        // Rows must ascend (non-strictly) by column for the merge: an entry
+        // and the next one of the strip, when they share the RowInStrip field
+        // (the same row), must not descend.
+        const uint32_t mask = (1u << bits) - 1u;
         bool bad = false;
 #pragma unroll
         for (int u = 0; u < E; ++u) {
             if (u >= umax) break;
-            const int j = s0 + q + G * u;
-            const int c_right = __shfl(c[u], lane + 1 < kWave ? lane + 1 : lane);
-            const int c_wrap = __shfl(c[u + 1 < E ? u + 1 : u], gbase);
-            const int cn = q + 1 < G ? c_right : c_wrap;
-            const int tn = t[u] + 1;
-            const int rpn_lane = __shfl(myrp, gbase + (tn < G ? tn : G - 1));
-            const int rpn = tn < nr ? rpn_lane : s1;
-            const bool act = valid && !special && j < s1;
-            // j + 1 < rpn: the next entry exists and lies in the same row (u + 1 < E
-            // whenever q == G - 1, because the strip holds at most G*E entries).
-            if (act && j + 1 < rpn && cn < c[u]) bad = true;
+            const int p = q + G * u;
+            if (fits && p + 1 < n) {
+                const uint32_t nw = static_cast<uint32_t>(A[p + 1] >> 32);
+                if ((nw & mask) == static_cast<uint32_t>(t[u]) && static_cast<int>(nw >> bits) < c[u]) bad = true;
+            }
         }
         const bool gbad = (ballot(bad) & group_mask(gbase, G)) != 0;
         special = special || (valid && gbad);
@@ -345,24 +364,7 @@ __global__ __launch_bounds__(kConvThreads) void from_csr_group_kernel(
                 ws_big[atomicAdd(&ws_count[1], 1)] = strip;
         }
         const bool go = valid && !special;
-        uint64_t* A = &lds[wave][gbase * E];
-        uint64_t* B = &lds[wave][kWave * E + gbase * E];
-        uint64_t key[E];
-        int pos[E];
-#pragma unroll
-        for (int u = 0; u < E; ++u) {
-            if (u >= umax) break;
-            const int p = q + G * u;
-            const uint32_t w = (static_cast<uint32_t>(c[u]) << bits) | static_cast<uint32_t>(t[u]);
-            key[u] = (static_cast<uint64_t>(w) << 32) | static_cast<uint32_t>(p);
-            pos[u] = p;
-            if (go && p < n) A[p] = key[u];
-        }
-        // Strip-relative row pointer of strip row x, 0 <= x <= HB (all lanes active).
-        auto rp = [&](int x) {
-            const int lv = __shfl(myrp, gbase + (x < G ? x : G - 1));
-            return (x < nr ? lv : s1) - s0;
-        };
+        auto rp = [&](int x) { return rtab[x]; };
 #pragma unroll 1
         for (int k = 0; (1 << k) < HB; ++k) {
             wave_lds_sync();
