@@ -37,6 +37,7 @@ HBM_PEAK_GBS = 8000.0
 SCHEDULES = {
     "group": ("auto", None),            # strip groups, non-temporal stream loads (library default)
     "wave": ("lds", None),              # one wave per strip, LDS partials (Algorithm 1 as printed)
+    "wave_nt": ("lds_nt", None),        # the same with non-temporal Val/word loads
     "colblock4": ("auto", 4),           # column-blocked, one launch, 4 blocks
     "colblock8": ("auto", 8),           # column-blocked, one launch, 8 blocks (one per XCD)
 }
