@@ -232,6 +232,10 @@ cmrs_status_t cmrs_spmv_colblock(const cmrs_mat_t *A, const void *x, void *y, cm
  * partial sums in LDS.  That LDS (64 lanes x partials x 8 bytes for fp64
  * values, 4 otherwise) must fit 64 KiB per wave: larger height-nrhs
  * combinations return CMRS_ERR_NOT_SUPPORTED.  X and Y must not overlap.
+ * Errors (nothing is enqueued): CMRS_ERR_INVALID_VALUE for a bad matrix
+ * descriptor, nrhs, leading dimension, group, NULL X/Y (when used) or
+ * overlapping X and Y; CMRS_ERR_NOT_SUPPORTED for a dtype pair other than
+ * the three above or the LDS limit; CMRS_ERR_DEVICE if the launch fails.
  */
 #define CMRS_SPMM_MAX_RHS 8
 cmrs_status_t cmrs_spmm(const cmrs_mat_t *A, int32_t nrhs, const void *X, int32_t ldx, void *Y, int32_t ldy,
@@ -248,8 +252,9 @@ cmrs_status_t cmrs_spmm(const cmrs_mat_t *A, int32_t nrhs, const void *X, int32_
  * empty: one queue per XCD over a contiguous eighth of the tile list, drained
  * first by that XCD's workgroups; the last wave to finish resets the queues,
  * so the same plan can be launched again, one launch at a time per plan, and
- * captured into a HIP graph.  Tile t of matrix i is computed exactly as cmrs_spmm computes those
- * strips with the plan's group width.
+ * captured into a HIP graph.  Tile t of matrix i is computed exactly as
+ * cmrs_spmm computes those strips with the plan's group width (clamped to
+ * 64), so results equal cmrs_spmm's bit for bit.
  *
  * cmrs_spmm_plan is set-up, not hot path: it copies the descriptor image
  * from host memory with hipMemcpyAsync and synchronises `stream` (so do not
@@ -259,6 +264,15 @@ cmrs_status_t cmrs_spmm(const cmrs_mat_t *A, int32_t nrhs, const void *X, int32_
  * value dtype, matched with xy_dtype as for cmrs_spmv.  Y_i must not overlap
  * each other or any X_j (X_j may be shared).  tuning may be NULL (defaults).
  * If a batched launch does not run to completion, rebuild the plan.
+ * Errors: cmrs_spmm_plan_bytes returns 0 for an invalid batch or tuning.
+ * cmrs_spmm_plan returns CMRS_ERR_INVALID_VALUE for a bad matrix, nrhs,
+ * leading dimension, tuning field, NULL array or overlapping outputs,
+ * CMRS_ERR_NOT_SUPPORTED for mixed value dtypes or the LDS limit of
+ * cmrs_spmm, CMRS_ERR_WORKSPACE when `desc` is NULL or smaller than
+ * cmrs_spmm_plan_bytes(), CMRS_ERR_DEVICE when the copy fails; on error
+ * nothing is written to `desc` or `plan`.  cmrs_spmm_batched returns
+ * CMRS_ERR_INVALID_VALUE for a plan whose fields are inconsistent (not
+ * filled by cmrs_spmm_plan) and CMRS_OK without launching for zero tiles.
  */
 typedef struct {
     int32_t tile_nnz;       /* stored entries per work tile (rounded to whole
@@ -351,9 +365,13 @@ cmrs_status_t cmrs_validate_csr(int32_t rows, int32_t cols, int32_t nnz, const i
  * wave per strip, 1 the same with non-temporal loads, 2 strip groups, 3
  * concurrent column blocks with 4 blocks; heights 1..32).
  *
- * cmrs_features: 40 floats from a CSR structure (row-length histogram, 20
- *   bins; |column - row*cols/rows| histogram, 16 bins; log sizes) — the bins
- *   are defined in csrc/select.hip.  workspace: CMRS_SEL_FEATURE_WS bytes.
+ * cmrs_features: 40 floats from a CSR structure: [0,20) fractions of rows
+ *   by length in half octaves (bin 0 empty; p = floor(log2 len) -> 1 + 2p,
+ *   or 2 + 2p when len >= 1.5 * 2^p; >= 512 -> 19); [20,36) fractions of
+ *   entries by |col - floor(row * cols / rows)| (0; then [2^(b-1), 2^b);
+ *   last bin open); 36..39 log2(rows)/22, log2(nnz+1)/26,
+ *   log2(nnz/rows+1)/14, log2(max len+1)/14.  workspace:
+ *   CMRS_SEL_FEATURE_WS bytes of device memory (zeroed by the call).
  * Parameters are one packed float array of CMRS_SEL_PARAMS:
  *   W1[40][64], b1[64], W2[64][64], b2[64], W3[64][24], b3[24] (row-major,
  *   out = in W + b).  Activations are [batch][width] row-major device arrays.
@@ -364,6 +382,11 @@ cmrs_status_t cmrs_validate_csr(int32_t rows, int32_t cols, int32_t nnz, const i
  * cmrs_mse_grad:     dY = scale * (Y - T), n values.
  * cmrs_adam_step:    one Adam update of n parameters (step >= 1 for the bias
  *   corrections).
+ * All arrays are caller-owned device fp32 arrays.  Errors: CMRS_ERR_INVALID_VALUE
+ * for a negative size (batch <= 0 for the backward), step < 1 or a NULL
+ * array; CMRS_ERR_WORKSPACE for a missing or short feature workspace;
+ * CMRS_ERR_DEVICE when a launch fails.  batch = 0 (forward) and n = 0 are
+ * no-ops.
  */
 #define CMRS_SEL_FEATURES 40
 #define CMRS_SEL_CLASSES 24
