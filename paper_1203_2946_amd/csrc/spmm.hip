@@ -360,18 +360,20 @@ hipError_t build_spmm_plan(int count, const cmrs_mat_t* mats, const int* nrhs, c
     const int bpc = blocks_per_cu > 0 ? blocks_per_cu : 4;
     const long long want_blocks = (static_cast<long long>(sh.tiles) + wpb - 1) / wpb;
     const int grid = static_cast<int>(std::max(1LL, std::min(static_cast<long long>(cus) * bpc, want_blocks)));
-    plan->count = count;
-    plan->tiles = sh.tiles;
-    plan->grid = sh.tiles > 0 ? grid : 0;
-    plan->lds_bytes = static_cast<int>(wave_bytes * wpb);
-    plan->val_dtype = count > 0 ? mats[0].val_dtype : CMRS_R64F;
-    plan->xy_dtype = xy_dtype;
-    plan->max_slots = std::max(1, sh.max_slots);
-    plan->waves = plan->grid * wpb;
-    plan->desc = desc;
-    plan->desc_bytes = sh.bytes;
+    cmrs_spmm_plan_t P{};
+    P.count = count;
+    P.tiles = sh.tiles;
+    P.grid = sh.tiles > 0 ? grid : 0;
+    P.lds_bytes = static_cast<int>(wave_bytes * wpb);
+    P.val_dtype = count > 0 ? mats[0].val_dtype : CMRS_R64F;
+    P.xy_dtype = xy_dtype;
+    P.max_slots = std::max(1, sh.max_slots);
+    P.waves = P.grid * wpb;
+    P.desc = desc;
+    P.desc_bytes = sh.bytes;
     e = hipMemcpyAsync(desc, image.data(), sh.bytes, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e == hipSuccess) *plan = P;
     return e;
 }
 
