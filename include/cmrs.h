@@ -269,8 +269,9 @@ cmrs_status_t cmrs_spmm(const cmrs_mat_t *A, int32_t nrhs, const void *X, int32_
  * leading dimension, tuning field, NULL array or overlapping outputs,
  * CMRS_ERR_NOT_SUPPORTED for mixed value dtypes or the LDS limit of
  * cmrs_spmm, CMRS_ERR_WORKSPACE when `desc` is NULL or smaller than
- * cmrs_spmm_plan_bytes(), CMRS_ERR_DEVICE when the copy fails; on error
- * nothing is written to `desc` or `plan`.  cmrs_spmm_batched returns
+ * cmrs_spmm_plan_bytes(), CMRS_ERR_DEVICE when the copy fails; `plan` is
+ * written only on success, `desc` not at all when a host-side check fails.
+ * cmrs_spmm_batched returns
  * CMRS_ERR_INVALID_VALUE for a plan whose fields are inconsistent (not
  * filled by cmrs_spmm_plan) and CMRS_OK without launching for zero tiles.
  */
