@@ -60,7 +60,7 @@ def parse():
     p.add_argument("--rows", type=int, default=1 << 20)
     p.add_argument("--no-extras", action="store_true",
                    help="skip the selector, batched, precision and padded reports")
-    p.add_argument("--only", choices=["batched", "precision"], default=None,
+    p.add_argument("--only", choices=["batched", "precision", "structured"], default=None,
                    help="run only that report (for profiling) and print it as one JSON line")
     p.add_argument("--batched-fixed", default=None,
                    help="skip the batched autotuner: dtype=height:tile_nnz:group:blocks_per_cu[,dtype=...]")
@@ -269,6 +269,43 @@ def precision_report():
     return out
 
 
+def structured_report():
+    """SpMV on two structured matrices whose gathers coalesce (a 27-point
+    stencil and a band matrix, 2*10^6 rows): what the kernels reach when the
+    workload streams rather than gathers (the paper's structured matrices
+    reach eta+ 0.8 on its hardware, its random permutation 0.09)."""
+    import torch
+    from paper_1203_2946_amd import cmrs, model
+    from synth import gpu_families as F
+    out = {}
+    g = torch.Generator(device="cuda")
+    for name, make in (("stencil27", lambda: F.stencil(2_000_000, g)),
+                       ("band_bw40", lambda: F.banded(2_000_000, g, bandwidth=40))):
+        g.manual_seed(3)
+        rp, ci, val, cols = make()
+        rows, nnz = rp.numel() - 1, ci.numel()
+        res = {"rows": rows, "nnz": nnz}
+        for dt, tdt, s in (("f64", torch.float64, 8), ("f32", torch.float32, 4)):
+            v = val.to(tdt)
+            x = torch.randn(cols, dtype=tdt, device="cuda")
+            best = None
+            for h in (4, 8, 16):
+                M = cmrs.from_csr(rp, ci, v, cols, h, sort=True)
+                for var in ("group_nt", "lds_nt"):
+                    tm = _median_ms(lambda: cmrs.spmv(M, x, variant=var))
+                    if best is None or tm < best[0]:
+                        best = (tm, h, var, M.strips)
+                del M
+            tm, h, var, strips = best
+            bp = model.beta_plus(nnz, rows, cols, strips, s, s, s)
+            res[dt] = {"height": h, "variant": var, "spmv_warm_ms": round(tm, 5), "gbs_plus": round(bp / tm / 1e6, 1),
+                       "eta_plus": round(bp / tm / 1e6 / HBM_PEAK_GBS, 4)}
+            log(f"structured {name} {dt}: h={h} {var} {tm * 1e3:.1f} us ({bp / tm / 1e6:.0f} GB/s)")
+        out[name] = res
+        del rp, ci, val
+    return out
+
+
 def padded_report(rp, ci, v64, x, cols, nnz, best_plain_ms):
     """Modified CMRS of Sec. 6.7 on this workload: memory overhead of the
     padding, conversion and SpMV times against the best plain SpMV."""
@@ -317,7 +354,8 @@ def main():
         print(json.dumps({"copy_calibration_bytes": a.numel() * 4, "copies": 3}), flush=True)
         return
     if args.only:
-        rep = batched_report(args.batched_fixed) if args.only == "batched" else precision_report()
+        rep = (batched_report(args.batched_fixed) if args.only == "batched"
+               else precision_report() if args.only == "precision" else structured_report())
         print(json.dumps({args.only: rep}), flush=True)
         return
     dev = torch.device("cuda:0")
@@ -550,6 +588,7 @@ def main():
         extras["padded"] = padded_report(rp, ci, v64, x_d["f64"], A.cols, A.nnz, best_plain)
         extras["selector"] = selector_report(rp, ci, v64, A.cols)
         extras["precision"] = precision_report()
+        extras["structured"] = structured_report()
         extras["batched"] = batched_report()
 
     out = {
