@@ -65,7 +65,9 @@ __global__ __launch_bounds__(256) void feature_count_kernel(int rows, int cols, 
     // One wave per 64-row group: lane l takes row r0 + l's length; the group's
     // entries are then walked by all 64 lanes, each entry's row found by a
     // binary search over the lanes' row pointers.
-    for (int r0 = (static_cast<int>(blockIdx.x) * 4 + wave) * kWave; r0 < rows; r0 += gridDim.x * 4 * kWave) {
+    for (long long r0l = (static_cast<long long>(blockIdx.x) * 4 + wave) * kWave; r0l < rows;
+         r0l += static_cast<long long>(gridDim.x) * 4 * kWave) {
+        const int r0 = static_cast<int>(r0l);
         const int nr = min(kWave, rows - r0);
         const int my = lane < nr ? row_ptr[r0 + lane] : 0x7fffffff;
         const int e0 = __shfl(my, 0);
