@@ -98,6 +98,45 @@ __device__ inline void bitonic_sort(uint64_t* k, int P, int tid, int nthreads, S
     }
 }
 
+// Merge of the sorted runs of one strip.  A[0..n) holds the keys (word << 32
+// | position) of a strip whose rows are each sorted by column; rt[x] is the
+// strip-relative start of strip row x (rt[x] = n for rows past the strip),
+// x = 0 .. HB.  Level k merges the runs of 2^k rows pairwise: each key finds
+// its place by counting the keys of the partner run below it (binary search;
+// keys of different runs never tie, their RowInStrip fields differ).
+// `nthreads` threads numbered `tid` run it; `sync` orders the levels.
+// Returns the buffer (A or B) that holds the merged strip.
+template <int HB, typename Sync>
+__device__ inline uint64_t* merge_strip_runs(uint64_t* A, uint64_t* B, int n, const int* rt, uint32_t mask,
+                                             int tid, int nthreads, Sync sync) {
+    for (int k = 0; (1 << k) < HB; ++k) {
+        for (int i = tid; i < n; i += nthreads) {
+            const uint64_t key = A[i];
+            const int t = static_cast<int>(static_cast<uint32_t>(key >> 32) & mask) & (HB - 1);
+            const int run = t >> k, partner = run ^ 1;
+            const int run_lo = rt[run << k];
+            const int merged_lo = rt[(run & ~1) << k];
+            const int p_lo = rt[partner << k], p_hi = rt[(partner + 1) << k];
+            int a = p_lo, len = p_hi - p_lo;
+            while (len > 0) {
+                const int half = len >> 1;
+                if (A[a + half] < key) {
+                    a += half + 1;
+                    len -= half + 1;
+                } else {
+                    len = half;
+                }
+            }
+            B[merged_lo + (i - run_lo) + (a - p_lo)] = key;
+        }
+        sync();
+        uint64_t* tmp = A;
+        A = B;
+        B = tmp;
+    }
+    return A;
+}
+
 // ------------------------------------------------------------------ whole-wave paths
 
 // Unsorted conversion of one strip by the whole wave, 8 loads per lane in
@@ -130,15 +169,18 @@ __device__ inline void pack_strip_wave(int strip, int rows, int height, int bits
 }
 
 // Sorted conversion of one strip of at most kWaveSortCap entries by the whole
-// wave, bitonic network in the wave's LDS slice k[kWaveSortCap].
+// wave in its LDS slice k[2 * kWaveSortCap]: when every row of the strip is
+// sorted by column, a merge of the row runs (merge_strip_runs); otherwise a
+// bitonic network.
 template <int HB, typename ET>
 __device__ inline void sort_strip_wave(int strip, int rows, int height, int bits, const int* __restrict__ row_ptr,
                                        const int* __restrict__ col_ind, const ET* __restrict__ val_in,
                                        uint32_t* __restrict__ col_word, ET* __restrict__ val_out, uint64_t* k,
-                                       int lane) {
+                                       int* rt, int lane) {
     const StripRows sr = load_strip_rows(strip, rows, height, row_ptr, lane);
     const int n = sr.s1 - sr.s0;
     const int P = pow2_at_least(n);
+    const uint32_t mask = (1u << bits) - 1u;
     for (int base = 0; base < P; base += kWave) {
         const int i = base + lane;
         const int r = row_in_strip<HB>(sr.myrp, sr.s0 + i, 0);
@@ -149,10 +191,22 @@ __device__ inline void sort_strip_wave(int strip, int rows, int height, int bits
             k[i] = ~0ull;
         }
     }
+    if (lane <= HB) rt[lane] = lane < sr.nr ? sr.myrp - sr.s0 : n;
     wave_lds_sync();
-    bitonic_sort(k, P, lane, kWave, [] { wave_lds_sync(); });
+    // Rows sorted: an entry and the next one, when in the same row, do not descend.
+    bool bad = false;
+    for (int i = lane; i + 1 < n; i += kWave) {
+        const uint32_t w0 = static_cast<uint32_t>(k[i] >> 32), w1 = static_cast<uint32_t>(k[i + 1] >> 32);
+        if ((w0 & mask) == (w1 & mask) && (w1 >> bits) < (w0 >> bits)) bad = true;
+    }
+    const uint64_t* res = k;
+    if (ballot(bad) == 0ull) {
+        res = merge_strip_runs<HB>(k, k + kWaveSortCap, n, rt, mask, lane, kWave, [] { wave_lds_sync(); });
+    } else {
+        bitonic_sort(k, P, lane, kWave, [] { wave_lds_sync(); });
+    }
     for (int i = lane; i < n; i += kWave) {
-        const uint64_t kk = k[i];
+        const uint64_t kk = res[i];
         col_word[sr.s0 + i] = static_cast<uint32_t>(kk >> 32);
         val_out[sr.s0 + i] = val_in[sr.s0 + static_cast<int>(static_cast<uint32_t>(kk))];
     }
@@ -544,62 +598,92 @@ __global__ __launch_bounds__(kConvThreads) void sort_list_wave_kernel(
     int rows, int height, int bits, const int* __restrict__ row_ptr, const int* __restrict__ col_ind,
     const ET* __restrict__ val_in, uint32_t* __restrict__ col_word, ET* __restrict__ val_out,
     const int* __restrict__ ws_count, const int* __restrict__ ws_small) {
-    __shared__ uint64_t keys[kConvWaves][kWaveSortCap];
+    __shared__ uint64_t keys[kConvWaves][2 * kWaveSortCap];
+    __shared__ int rtab[kConvWaves][HB + 1];
     const int lane = lane_id();
     const int wave = uniform(static_cast<int>(threadIdx.x) / kWave);
     const int count = ws_count[0];
     const int nwaves = static_cast<int>(gridDim.x) * kConvWaves;
     for (int item = static_cast<int>(blockIdx.x) * kConvWaves + wave; item < count; item += nwaves)
         sort_strip_wave<HB, ET>(ws_small[item], rows, height, bits, row_ptr, col_ind, val_in, col_word, val_out,
-                                keys[wave], lane);
+                                keys[wave], rtab[wave], lane);
 }
 
 // Sorted conversion of the listed long strips: one 1024-thread workgroup per
-// strip, strips taken in a grid-stride loop.
+// strip, strips taken in a grid-stride loop.  Strips whose rows are sorted by
+// column are merged run by run (merge_strip_runs) in LDS when both buffers fit
+// (n <= kBlockSortCap / 2), and in the strip's own slice of the workspace
+// [2*s0, 2*s1) when they do not fit in LDS at all (n > kBlockSortCap); the
+// others are sorted by a bitonic network in LDS (n <= kBlockSortCap) or in
+// that slice.
 template <int HB, typename ET>
 __global__ __launch_bounds__(kBlockSortThreads) void sort_list_block_kernel(
     int rows, int height, int bits, const int* __restrict__ row_ptr, const int* __restrict__ col_ind,
     const ET* __restrict__ val_in, uint32_t* __restrict__ col_word, ET* __restrict__ val_out,
     const int* __restrict__ ws_count, const int* __restrict__ ws_big, uint64_t* __restrict__ gkeys) {
     __shared__ uint64_t skeys[kBlockSortCap];
+    __shared__ int rt[HB + 1];
+    const int tid = static_cast<int>(threadIdx.x);
     const int lane = lane_id();
-    const int wave = static_cast<int>(threadIdx.x) / kWave;
+    const int wave = tid / kWave;
     const int count = ws_count[1];
+    const uint32_t mask = (1u << bits) - 1u;
+    auto lds_sync = [] { __syncthreads(); };
+    auto global_sync = [] {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+        __syncthreads();
+    };
     for (int item = blockIdx.x; item < count; item += gridDim.x) {
         const int strip = ws_big[item];
         const StripRows sr = load_strip_rows(strip, rows, height, row_ptr, lane);
         const int n = sr.s1 - sr.s0;
-        const int P = pow2_at_least(n);
+        // Keys in order, with the canonical-row check on the way: entry i and
+        // i + 1 of one row must not descend by column.
+        uint64_t* slice = gkeys + 2 * static_cast<size_t>(sr.s0);
         const bool in_lds = n <= kBlockSortCap;
-        // P <= 2n, so [2*s0, 2*s0 + P) lies inside this strip's own slice [2*s0, 2*s1).
-        uint64_t* k = in_lds ? skeys : gkeys + 2 * static_cast<size_t>(sr.s0);
-        for (int base = wave * kWave; base < P; base += kBlockSortThreads) {
+        const bool merge_in_lds = 2 * n <= kBlockSortCap;
+        uint64_t* A = in_lds ? skeys : slice;
+        bool bad = false;
+        for (int base = wave * kWave; base < n; base += kBlockSortThreads) {
             const int i = base + lane;
             const int r = row_in_strip<HB>(sr.myrp, sr.s0 + i, 0);
+            const int rn = row_in_strip<HB>(sr.myrp, sr.s0 + i + 1, 0);
             if (i < n) {
-                const uint32_t w = (static_cast<uint32_t>(col_ind[sr.s0 + i]) << bits) | static_cast<uint32_t>(r);
-                k[i] = (static_cast<uint64_t>(w) << 32) | static_cast<uint32_t>(i);
-            } else if (i < P) {
-                k[i] = ~0ull;
+                const int c = col_ind[sr.s0 + i];
+                const uint32_t w = (static_cast<uint32_t>(c) << bits) | static_cast<uint32_t>(r);
+                A[i] = (static_cast<uint64_t>(w) << 32) | static_cast<uint32_t>(i);
+                if (i + 1 < n && rn == r && col_ind[sr.s0 + i + 1] < c) bad = true;
             }
         }
-        if (in_lds) {
-            __syncthreads();
-            bitonic_sort(k, P, static_cast<int>(threadIdx.x), kBlockSortThreads, [] { __syncthreads(); });
+        if (tid <= HB) rt[tid] = tid < sr.nr ? sr.myrp - sr.s0 : n;  // wave 0: lane == tid
+        if (!in_lds) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+        const bool any_bad = __syncthreads_or(bad) != 0;
+        const uint64_t* res;
+        if (!any_bad && merge_in_lds) {
+            res = merge_strip_runs<HB>(A, skeys + n, n, rt, mask, tid, kBlockSortThreads, lds_sync);
+        } else if (!any_bad && !in_lds) {
+            res = merge_strip_runs<HB>(A, slice + n, n, rt, mask, tid, kBlockSortThreads, global_sync);
         } else {
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
-            __syncthreads();
-            bitonic_sort(k, P, static_cast<int>(threadIdx.x), kBlockSortThreads, [] {
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+            // Bitonic network over P = pow2(n) <= 2n keys (padding = max key),
+            // in place in A (LDS up to kBlockSortCap entries, else the slice).
+            const int P = pow2_at_least(n);
+            uint64_t* k = A;
+            for (int i = n + tid; i < P; i += kBlockSortThreads) k[i] = ~0ull;
+            if (in_lds) {
                 __syncthreads();
-            });
+                bitonic_sort(k, P, tid, kBlockSortThreads, lds_sync);
+            } else {
+                global_sync();
+                bitonic_sort(k, P, tid, kBlockSortThreads, global_sync);
+            }
+            res = k;
         }
-        for (int i = static_cast<int>(threadIdx.x); i < n; i += kBlockSortThreads) {
-            const uint64_t kk = k[i];
+        for (int i = tid; i < n; i += kBlockSortThreads) {
+            const uint64_t kk = res[i];
             col_word[sr.s0 + i] = static_cast<uint32_t>(kk >> 32);
             val_out[sr.s0 + i] = val_in[sr.s0 + static_cast<int>(static_cast<uint32_t>(kk))];
         }
-        __syncthreads();  // the next item reuses skeys
+        __syncthreads();  // the next item reuses skeys and rt
     }
 }
 
