@@ -168,11 +168,10 @@ __device__ inline void pack_strip_wave(int strip, int rows, int height, int bits
     }
 }
 
-// Sorted conversion of one strip of at most kWaveSortCap entries by the whole
-// wave in its LDS slice k[2 * kWaveSortCap]: when every row of the strip is
-// sorted by column, a merge of the row runs (merge_strip_runs); otherwise a
-// bitonic network.
-template <int HB, typename ET>
+// Sorted conversion of one strip of at most CAPW entries by the whole wave in
+// its LDS slice k[2 * CAPW]: when every row of the strip is sorted by column, a
+// merge of the row runs (merge_strip_runs); otherwise a bitonic network.
+template <int HB, int CAPW, typename ET>
 __device__ inline void sort_strip_wave(int strip, int rows, int height, int bits, const int* __restrict__ row_ptr,
                                        const int* __restrict__ col_ind, const ET* __restrict__ val_in,
                                        uint32_t* __restrict__ col_word, ET* __restrict__ val_out, uint64_t* k,
@@ -201,7 +200,7 @@ __device__ inline void sort_strip_wave(int strip, int rows, int height, int bits
     }
     const uint64_t* res = k;
     if (ballot(bad) == 0ull) {
-        res = merge_strip_runs<HB>(k, k + kWaveSortCap, n, rt, mask, lane, kWave, [] { wave_lds_sync(); });
+        res = merge_strip_runs<HB>(k, k + CAPW, n, rt, mask, lane, kWave, [] { wave_lds_sync(); });
     } else {
         bitonic_sort(k, P, lane, kWave, [] { wave_lds_sync(); });
     }
@@ -303,8 +302,10 @@ __device__ inline int used_slots(int n) {
 
 // CSR -> CMRS for strips of at most G*E entries, G lanes per strip.
 // Writes strip_ptr too.  Unsorted: longer strips are packed by the whole
-// wave afterwards.  Sorted: longer or unsorted-row strips go to the workspace
-// lists (ws_count[0] / ws_small: at most kWaveSortCap entries; ws_count[1] /
+// wave afterwards.  Sorted: longer strips of at most kWave*E entries and
+// strips with unsorted rows are sorted by the whole wave afterwards in the
+// wave's LDS slice; still longer ones go to the workspace lists
+// (ws_count[0] / ws_small: at most kWaveSortCap entries; ws_count[1] /
 // ws_big: longer).  col_word may alias col_ind and val_out may alias val_in
 // only when unsorted.
 template <int HB, int G, int E, bool SORT, typename ET>
@@ -411,7 +412,8 @@ __global__ __launch_bounds__(kConvThreads) void from_csr_group_kernel(
         }
         const bool gbad = (ballot(bad) & group_mask(gbase, G)) != 0;
         special = special || (valid && gbad);
-        if (valid && special && q == 0) {
+        constexpr int WCAP = kWave * E;
+        if (valid && special && q == 0 && n > WCAP) {
             if (n <= kWaveSortCap)
                 ws_small[atomicAdd(&ws_count[0], 1)] = strip;
             else
@@ -468,6 +470,14 @@ __global__ __launch_bounds__(kConvThreads) void from_csr_group_kernel(
                 col_word[s0 + i] = static_cast<uint32_t>(kk >> 32);
                 val_out[s0 + i] = static_cast<ET>(B[static_cast<uint32_t>(kk)]);
             }
+        }
+        wave_lds_sync();  // the wave's slice is reused below
+        uint64_t mids = ballot(valid && special && q == 0 && n <= WCAP);
+        while (mids) {
+            const int leader = __ffsll(static_cast<unsigned long long>(mids)) - 1;
+            mids &= mids - 1;
+            sort_strip_wave<HB, WCAP, ET>(strip0 + leader / G, rows, height, bits, row_ptr, col_ind, val_in,
+                                          col_word, val_out, lds[wave], rowtab[wave], lane);
         }
     }
 }
@@ -605,17 +615,71 @@ __global__ __launch_bounds__(kConvThreads) void sort_list_wave_kernel(
     const int count = ws_count[0];
     const int nwaves = static_cast<int>(gridDim.x) * kConvWaves;
     for (int item = static_cast<int>(blockIdx.x) * kConvWaves + wave; item < count; item += nwaves)
-        sort_strip_wave<HB, ET>(ws_small[item], rows, height, bits, row_ptr, col_ind, val_in, col_word, val_out,
-                                keys[wave], rtab[wave], lane);
+        sort_strip_wave<HB, kWaveSortCap, ET>(ws_small[item], rows, height, bits, row_ptr, col_ind, val_in, col_word,
+                                              val_out, keys[wave], rtab[wave], lane);
+}
+
+// One listed long strip of n entries by the whole 1024-thread workgroup, keys
+// in A (n entries) with B (n entries) as the second merge buffer.  Strips whose
+// rows are sorted by column are merged run by run (merge_strip_runs); the
+// others are sorted by a bitonic network in place in A, which then needs room
+// for pow2(n) <= 2n keys.  keys_global / merge_global say whether A / B lie in
+// global memory (the strip's workspace slice), whose passes then need an
+// agent-scope fence before the barrier.  Forced inline, so that each call
+// site keeps LDS buffers in the LDS address space.
+template <int HB, typename ET>
+__device__ __forceinline__ void sort_strip_block(const StripRows& sr, int n, int bits,
+                                                 const int* __restrict__ col_ind, const ET* __restrict__ val_in,
+                                                 uint32_t* __restrict__ col_word, ET* __restrict__ val_out,
+                                                 uint64_t* A, uint64_t* B, bool keys_global, bool merge_global,
+                                                 int* rt, int tid, int wave, int lane) {
+    const uint32_t mask = (1u << bits) - 1u;
+    // Keys in order, with the canonical-row check on the way: entry i and
+    // i + 1 of one row must not descend by column.
+    bool bad = false;
+    for (int base = wave * kWave; base < n; base += kBlockSortThreads) {
+        const int i = base + lane;
+        const int r = row_in_strip<HB>(sr.myrp, sr.s0 + i, 0);
+        const int rn = row_in_strip<HB>(sr.myrp, sr.s0 + i + 1, 0);
+        if (i < n) {
+            const int c = col_ind[sr.s0 + i];
+            const uint32_t w = (static_cast<uint32_t>(c) << bits) | static_cast<uint32_t>(r);
+            A[i] = (static_cast<uint64_t>(w) << 32) | static_cast<uint32_t>(i);
+            if (i + 1 < n && rn == r && col_ind[sr.s0 + i + 1] < c) bad = true;
+        }
+    }
+    if (tid <= HB) rt[tid] = tid < sr.nr ? sr.myrp - sr.s0 : n;  // wave 0: lane == tid
+    if (keys_global) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+    const bool any_bad = __syncthreads_or(bad) != 0;
+    const uint64_t* res;
+    if (!any_bad) {
+        res = merge_strip_runs<HB>(A, B, n, rt, mask, tid, kBlockSortThreads, [merge_global] {
+            if (merge_global) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+            __syncthreads();
+        });
+    } else {
+        const int P = pow2_at_least(n);
+        for (int i = n + tid; i < P; i += kBlockSortThreads) A[i] = ~0ull;
+        const auto sync = [keys_global] {
+            if (keys_global) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+            __syncthreads();
+        };
+        sync();
+        bitonic_sort(A, P, tid, kBlockSortThreads, sync);
+        res = A;
+    }
+    for (int i = tid; i < n; i += kBlockSortThreads) {
+        const uint64_t kk = res[i];
+        col_word[sr.s0 + i] = static_cast<uint32_t>(kk >> 32);
+        val_out[sr.s0 + i] = val_in[sr.s0 + static_cast<int>(static_cast<uint32_t>(kk))];
+    }
 }
 
 // Sorted conversion of the listed long strips: one 1024-thread workgroup per
-// strip, strips taken in a grid-stride loop.  Strips whose rows are sorted by
-// column are merged run by run (merge_strip_runs) in LDS when both buffers fit
-// (n <= kBlockSortCap / 2), and in the strip's own slice of the workspace
-// [2*s0, 2*s1) when they do not fit in LDS at all (n > kBlockSortCap); the
-// others are sorted by a bitonic network in LDS (n <= kBlockSortCap) or in
-// that slice.
+// strip, strips taken in a grid-stride loop.  The keys live in LDS when the
+// strip fits (n <= kBlockSortCap), else in the strip's own slice of the
+// workspace [2*s0, 2*s1); the merge's second buffer is LDS when both fit
+// (n <= kBlockSortCap / 2), else that slice.
 template <int HB, typename ET>
 __global__ __launch_bounds__(kBlockSortThreads) void sort_list_block_kernel(
     int rows, int height, int bits, const int* __restrict__ row_ptr, const int* __restrict__ col_ind,
@@ -627,62 +691,19 @@ __global__ __launch_bounds__(kBlockSortThreads) void sort_list_block_kernel(
     const int lane = lane_id();
     const int wave = tid / kWave;
     const int count = ws_count[1];
-    const uint32_t mask = (1u << bits) - 1u;
-    auto lds_sync = [] { __syncthreads(); };
-    auto global_sync = [] {
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
-        __syncthreads();
-    };
     for (int item = blockIdx.x; item < count; item += gridDim.x) {
-        const int strip = ws_big[item];
-        const StripRows sr = load_strip_rows(strip, rows, height, row_ptr, lane);
+        const StripRows sr = load_strip_rows(ws_big[item], rows, height, row_ptr, lane);
         const int n = sr.s1 - sr.s0;
-        // Keys in order, with the canonical-row check on the way: entry i and
-        // i + 1 of one row must not descend by column.
         uint64_t* slice = gkeys + 2 * static_cast<size_t>(sr.s0);
-        const bool in_lds = n <= kBlockSortCap;
-        const bool merge_in_lds = 2 * n <= kBlockSortCap;
-        uint64_t* A = in_lds ? skeys : slice;
-        bool bad = false;
-        for (int base = wave * kWave; base < n; base += kBlockSortThreads) {
-            const int i = base + lane;
-            const int r = row_in_strip<HB>(sr.myrp, sr.s0 + i, 0);
-            const int rn = row_in_strip<HB>(sr.myrp, sr.s0 + i + 1, 0);
-            if (i < n) {
-                const int c = col_ind[sr.s0 + i];
-                const uint32_t w = (static_cast<uint32_t>(c) << bits) | static_cast<uint32_t>(r);
-                A[i] = (static_cast<uint64_t>(w) << 32) | static_cast<uint32_t>(i);
-                if (i + 1 < n && rn == r && col_ind[sr.s0 + i + 1] < c) bad = true;
-            }
-        }
-        if (tid <= HB) rt[tid] = tid < sr.nr ? sr.myrp - sr.s0 : n;  // wave 0: lane == tid
-        if (!in_lds) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
-        const bool any_bad = __syncthreads_or(bad) != 0;
-        const uint64_t* res;
-        if (!any_bad && merge_in_lds) {
-            res = merge_strip_runs<HB>(A, skeys + n, n, rt, mask, tid, kBlockSortThreads, lds_sync);
-        } else if (!any_bad && !in_lds) {
-            res = merge_strip_runs<HB>(A, slice + n, n, rt, mask, tid, kBlockSortThreads, global_sync);
-        } else {
-            // Bitonic network over P = pow2(n) <= 2n keys (padding = max key),
-            // in place in A (LDS up to kBlockSortCap entries, else the slice).
-            const int P = pow2_at_least(n);
-            uint64_t* k = A;
-            for (int i = n + tid; i < P; i += kBlockSortThreads) k[i] = ~0ull;
-            if (in_lds) {
-                __syncthreads();
-                bitonic_sort(k, P, tid, kBlockSortThreads, lds_sync);
-            } else {
-                global_sync();
-                bitonic_sort(k, P, tid, kBlockSortThreads, global_sync);
-            }
-            res = k;
-        }
-        for (int i = tid; i < n; i += kBlockSortThreads) {
-            const uint64_t kk = res[i];
-            col_word[sr.s0 + i] = static_cast<uint32_t>(kk >> 32);
-            val_out[sr.s0 + i] = val_in[sr.s0 + static_cast<int>(static_cast<uint32_t>(kk))];
-        }
+        if (2 * n <= kBlockSortCap)
+            sort_strip_block<HB, ET>(sr, n, bits, col_ind, val_in, col_word, val_out, skeys, skeys + n, false,
+                                     false, rt, tid, wave, lane);
+        else if (n <= kBlockSortCap)
+            sort_strip_block<HB, ET>(sr, n, bits, col_ind, val_in, col_word, val_out, skeys, slice, false, true, rt,
+                                     tid, wave, lane);
+        else
+            sort_strip_block<HB, ET>(sr, n, bits, col_ind, val_in, col_word, val_out, slice, slice + n, true, true,
+                                     rt, tid, wave, lane);
         __syncthreads();  // the next item reuses skeys and rt
     }
 }
