@@ -98,45 +98,6 @@ __device__ inline void bitonic_sort(uint64_t* k, int P, int tid, int nthreads, S
     }
 }
 
-// Merge of the sorted runs of one strip.  A[0..n) holds the keys (word << 32
-// | position) of a strip whose rows are each sorted by column; rt[x] is the
-// strip-relative start of strip row x (rt[x] = n for rows past the strip),
-// x = 0 .. HB.  Level k merges the runs of 2^k rows pairwise: each key finds
-// its place by counting the keys of the partner run below it (binary search;
-// keys of different runs never tie, their RowInStrip fields differ).
-// `nthreads` threads numbered `tid` run it; `sync` orders the levels.
-// Returns the buffer (A or B) that holds the merged strip.
-template <int HB, typename Sync>
-__device__ inline uint64_t* merge_strip_runs(uint64_t* A, uint64_t* B, int n, const int* rt, uint32_t mask,
-                                             int tid, int nthreads, Sync sync) {
-    for (int k = 0; (1 << k) < HB; ++k) {
-        for (int i = tid; i < n; i += nthreads) {
-            const uint64_t key = A[i];
-            const int t = static_cast<int>(static_cast<uint32_t>(key >> 32) & mask) & (HB - 1);
-            const int run = t >> k, partner = run ^ 1;
-            const int run_lo = rt[run << k];
-            const int merged_lo = rt[(run & ~1) << k];
-            const int p_lo = rt[partner << k], p_hi = rt[(partner + 1) << k];
-            int a = p_lo, len = p_hi - p_lo;
-            while (len > 0) {
-                const int half = len >> 1;
-                if (A[a + half] < key) {
-                    a += half + 1;
-                    len -= half + 1;
-                } else {
-                    len = half;
-                }
-            }
-            B[merged_lo + (i - run_lo) + (a - p_lo)] = key;
-        }
-        sync();
-        uint64_t* tmp = A;
-        A = B;
-        B = tmp;
-    }
-    return A;
-}
-
 // ------------------------------------------------------------------ whole-wave paths
 
 // Unsorted conversion of one strip by the whole wave, 8 loads per lane in
@@ -168,46 +129,123 @@ __device__ inline void pack_strip_wave(int strip, int rows, int height, int bits
     }
 }
 
-// Sorted conversion of one strip of at most CAPW entries by the whole wave in
-// its LDS slice k[2 * CAPW]: when every row of the strip is sorted by column, a
-// merge of the row runs (merge_strip_runs); otherwise a bitonic network.
-template <int HB, int CAPW, typename ET>
-__device__ inline void sort_strip_wave(int strip, int rows, int height, int bits, const int* __restrict__ row_ptr,
-                                       const int* __restrict__ col_ind, const ET* __restrict__ val_in,
-                                       uint32_t* __restrict__ col_word, ET* __restrict__ val_out, uint64_t* k,
-                                       int* rt, int lane) {
+// Merge of the row runs of strips held in registers, G lanes per strip, slot u
+// of lane q holding entry q + G*u: words (col << bits | RowInStrip) in wd and
+// their current place in the strip in pos.  LDS
+// buffers A and B (the group's words by place, A filled on entry) alternate
+// per level, level k merging the runs of 2^k rows pairwise; the words of
+// different runs never tie (their RowInStrip fields differ), so
+// an entry's place after a level is its rank in its own run plus the number
+// of partner-run words below it.  On return pos holds each entry's place in
+// the sorted strip.  The caller has made A and rt visible to the wave.
+template <int HB, int G, int E>
+__device__ inline void merge_runs_regs(uint32_t* A, uint32_t* B, const int* rt, const uint32_t (&wd)[E],
+                                       int (&pos)[E], int umax, bool go, int n, int q) {
+#pragma unroll 1
+    for (int k = 0; (1 << k) < HB; ++k) {
+        if (k > 0) wave_lds_sync();
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            if (u >= umax) break;
+            const int run = static_cast<int>(wd[u] & static_cast<uint32_t>(HB - 1)) >> k;
+            const int partner = run ^ 1;
+            const int run_lo = rt[run << k];
+            const int merged_lo = rt[(run & ~1) << k];
+            const int p_lo = rt[partner << k];
+            const int p_hi = rt[(partner + 1) << k];
+            if (go && q + G * u < n) {
+                int a = p_lo, len = p_hi - p_lo;
+                while (len > 0) {
+                    const int half = len >> 1;
+                    if (A[a + half] < wd[u]) {
+                        a += half + 1;
+                        len -= half + 1;
+                    } else {
+                        len = half;
+                    }
+                }
+                pos[u] = merged_lo + (pos[u] - run_lo) + (a - p_lo);
+                B[pos[u]] = wd[u];
+            }
+        }
+        uint32_t* tmp = A;
+        A = B;
+        B = tmp;
+    }
+}
+
+// Sorted conversion of one strip of at most kWave*E entries by the whole wave,
+// words in registers (slot u of lane l: entry l + kWave*u), in its LDS slice
+// of kWave*E 64-bit words: rows sorted by column, a merge of the row runs
+// (merge_runs_regs), then each entry and its value (read again) to its place;
+// otherwise a bitonic network over (word, position) keys.
+template <int HB, int E, typename ET>
+__device__ inline void sort_strip_mid(int strip, int rows, int height, int bits, const int* __restrict__ row_ptr,
+                                      const int* __restrict__ col_ind, const ET* __restrict__ val_in,
+                                      uint32_t* __restrict__ col_word, ET* __restrict__ val_out, uint64_t* slice,
+                                      int* rt, int lane) {
     const StripRows sr = load_strip_rows(strip, rows, height, row_ptr, lane);
     const int n = sr.s1 - sr.s0;
-    const int P = pow2_at_least(n);
+    const int umax = uniform((n + kWave - 1) / kWave);
     const uint32_t mask = (1u << bits) - 1u;
-    for (int base = 0; base < P; base += kWave) {
-        const int i = base + lane;
-        const int r = row_in_strip<HB>(sr.myrp, sr.s0 + i, 0);
-        if (i < n) {
-            const uint32_t w = (static_cast<uint32_t>(col_ind[sr.s0 + i]) << bits) | static_cast<uint32_t>(r);
-            k[i] = (static_cast<uint64_t>(w) << 32) | static_cast<uint32_t>(i);
-        } else if (i < P) {
-            k[i] = ~0ull;
+    uint32_t* A = reinterpret_cast<uint32_t*>(slice);
+    uint32_t* B = A + kWave * E;
+    uint32_t wd[E];
+    int pos[E];
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+        wd[u] = 0u;
+        pos[u] = lane + kWave * u;
+        if (u < umax) {
+            const int i = lane + kWave * u;
+            const int r = row_in_strip<HB>(sr.myrp, sr.s0 + i, 0);
+            if (i < n) {
+                wd[u] = (static_cast<uint32_t>(col_ind[sr.s0 + i]) << bits) | static_cast<uint32_t>(r);
+                A[i] = wd[u];
+            }
         }
     }
     if (lane <= HB) rt[lane] = lane < sr.nr ? sr.myrp - sr.s0 : n;
     wave_lds_sync();
-    // Rows sorted: an entry and the next one, when in the same row, do not descend.
     bool bad = false;
-    for (int i = lane; i + 1 < n; i += kWave) {
-        const uint32_t w0 = static_cast<uint32_t>(k[i] >> 32), w1 = static_cast<uint32_t>(k[i + 1] >> 32);
-        if ((w0 & mask) == (w1 & mask) && (w1 >> bits) < (w0 >> bits)) bad = true;
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+        if (u >= umax) break;
+        const int i = lane + kWave * u;
+        if (i + 1 < n) {
+            const uint32_t nw = A[i + 1];
+            if ((nw & mask) == (wd[u] & mask) && (nw >> bits) < (wd[u] >> bits)) bad = true;
+        }
     }
-    const uint64_t* res = k;
     if (ballot(bad) == 0ull) {
-        res = merge_strip_runs<HB>(k, k + CAPW, n, rt, mask, lane, kWave, [] { wave_lds_sync(); });
+        merge_runs_regs<HB, kWave, E>(A, B, rt, wd, pos, umax, true, n, lane);
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            if (u >= umax) break;
+            const int i = lane + kWave * u;
+            if (i < n && static_cast<unsigned>(pos[u]) < static_cast<unsigned>(n)) {
+                col_word[sr.s0 + pos[u]] = wd[u];
+                val_out[sr.s0 + pos[u]] = val_in[sr.s0 + i];
+            }
+        }
     } else {
-        bitonic_sort(k, P, lane, kWave, [] { wave_lds_sync(); });
-    }
-    for (int i = lane; i < n; i += kWave) {
-        const uint64_t kk = res[i];
-        col_word[sr.s0 + i] = static_cast<uint32_t>(kk >> 32);
-        val_out[sr.s0 + i] = val_in[sr.s0 + static_cast<int>(static_cast<uint32_t>(kk))];
+        const int P = pow2_at_least(n);
+        wave_lds_sync();  // A is read above; the keys overwrite it
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            const int i = lane + kWave * u;
+            if (i < n)
+                slice[i] = (static_cast<uint64_t>(wd[u]) << 32) | static_cast<uint32_t>(i);
+            else if (i < P)
+                slice[i] = ~0ull;
+        }
+        wave_lds_sync();
+        bitonic_sort(slice, P, lane, kWave, [] { wave_lds_sync(); });
+        for (int i = lane; i < n; i += kWave) {
+            const uint64_t kk = slice[i];
+            col_word[sr.s0 + i] = static_cast<uint32_t>(kk >> 32);
+            val_out[sr.s0 + i] = val_in[sr.s0 + static_cast<int>(static_cast<uint32_t>(kk))];
+        }
     }
     wave_lds_sync();
 }
@@ -309,14 +347,14 @@ __device__ inline int used_slots(int n) {
 // ws_big: longer).  col_word may alias col_ind and val_out may alias val_in
 // only when unsorted.
 template <int HB, int G, int E, bool SORT, typename ET>
-__global__ __launch_bounds__(kConvThreads) void from_csr_group_kernel(
+__global__ __launch_bounds__(kConvThreads) __attribute__((amdgpu_waves_per_eu(8))) void from_csr_group_kernel(
     int rows, int strips, int height, int bits, int nnz, const int* __restrict__ row_ptr, const int* col_ind,
     const ET* val_in, int* __restrict__ strip_ptr, uint32_t* col_word, ET* val_out, int copy_val,
     int* __restrict__ ws_count, int* __restrict__ ws_small, int* __restrict__ ws_big) {
     static_assert(G >= HB && G <= kWave && G >= 2, "group width");
     constexpr int NG = kWave / G;
     constexpr int CAP = G * E;
-    __shared__ uint64_t lds[SORT ? kConvWaves : 1][SORT ? 2 * kWave * E : 1];
+    __shared__ uint64_t lds[SORT ? kConvWaves : 1][SORT ? kWave * E : 1];
     __shared__ int rowtab[SORT ? kConvWaves : 1][SORT ? NG * (HB + 1) : 1];
     const int lane = lane_id();
     const int wave = uniform(static_cast<int>(threadIdx.x) / kWave);
@@ -375,23 +413,20 @@ __global__ __launch_bounds__(kConvThreads) void from_csr_group_kernel(
         }
         return;
     } else {
-        // Keys (word << 32 | position in strip) of every strip the group holds,
-        // and the strip-relative row pointers of rows 0..HB (rows past the
-        // strip: n), in LDS.
+        // Words of every strip the group holds in LDS by place, and the
+        // strip-relative row pointers of rows 0..HB (rows past the strip: n).
         const bool fits = valid && !special;
-        uint64_t* A = &lds[wave][gbase * E];
-        uint64_t* B = &lds[wave][kWave * E + gbase * E];
+        uint32_t* A = reinterpret_cast<uint32_t*>(&lds[wave][0]) + gbase * E;
+        uint32_t* B = reinterpret_cast<uint32_t*>(&lds[wave][0]) + kWave * E + gbase * E;
         int* rtab = &rowtab[wave][g * (HB + 1)];
-        uint64_t key[E];
+        uint32_t wd[E];
         int pos[E];
 #pragma unroll
         for (int u = 0; u < E; ++u) {
-            if (u >= umax) break;
             const int p = q + G * u;
-            const uint32_t w = (static_cast<uint32_t>(c[u]) << bits) | static_cast<uint32_t>(t[u]);
-            key[u] = (static_cast<uint64_t>(w) << 32) | static_cast<uint32_t>(p);
+            wd[u] = (static_cast<uint32_t>(c[u]) << bits) | static_cast<uint32_t>(t[u]);
             pos[u] = p;
-            if (fits && p < n) A[p] = key[u];
+            if (u < umax && fits && p < n) A[p] = wd[u];
         }
         if (q < HB) rtab[q] = q < nr ? myrp - s0 : n;
         if (q == 0) rtab[HB] = n;
@@ -406,8 +441,8 @@ __global__ __launch_bounds__(kConvThreads) void from_csr_group_kernel(
             if (u >= umax) break;
             const int p = q + G * u;
             if (fits && p + 1 < n) {
-                const uint32_t nw = static_cast<uint32_t>(A[p + 1] >> 32);
-                if ((nw & mask) == static_cast<uint32_t>(t[u]) && static_cast<int>(nw >> bits) < c[u]) bad = true;
+                const uint32_t nw = A[p + 1];
+                if ((nw & mask) == (wd[u] & mask) && (nw >> bits) < (wd[u] >> bits)) bad = true;
             }
         }
         const bool gbad = (ballot(bad) & group_mask(gbase, G)) != 0;
@@ -420,55 +455,14 @@ __global__ __launch_bounds__(kConvThreads) void from_csr_group_kernel(
                 ws_big[atomicAdd(&ws_count[1], 1)] = strip;
         }
         const bool go = valid && !special;
-        auto rp = [&](int x) { return rtab[x]; };
-#pragma unroll 1
-        for (int k = 0; (1 << k) < HB; ++k) {
-            wave_lds_sync();
-#pragma unroll
-            for (int u = 0; u < E; ++u) {
-                if (u >= umax) break;
-                const int run = t[u] >> k;
-                const int partner = run ^ 1;
-                const int run_lo = rp(run << k);
-                const int merged_lo = rp((run & ~1) << k);
-                const int p_lo = rp(partner << k);
-                const int p_hi = rp((partner + 1) << k);
-                if (go && q + G * u < n) {
-                    int a = p_lo, len = p_hi - p_lo;
-                    while (len > 0) {
-                        const int half = len >> 1;
-                        if (A[a + half] < key[u]) {
-                            a += half + 1;
-                            len -= half + 1;
-                        } else {
-                            len = half;
-                        }
-                    }
-                    pos[u] = merged_lo + (pos[u] - run_lo) + (a - p_lo);
-                    B[pos[u]] = key[u];
-                }
-            }
-            uint64_t* tmp = A;
-            A = B;
-            B = tmp;
-        }
-        wave_lds_sync();
-        // Values by original position into the free buffer, then out in sorted order.
+        merge_runs_regs<HB, G, E>(A, B, rtab, wd, pos, umax, go, n, q);
+        // Out from registers: each entry to its place in the sorted strip.
 #pragma unroll
         for (int u = 0; u < E; ++u) {
             if (u >= umax) break;
-            const int p = q + G * u;
-            if (go && p < n) B[p] = static_cast<uint64_t>(v[u]);
-        }
-        wave_lds_sync();
-#pragma unroll
-        for (int u = 0; u < E; ++u) {
-            if (u >= umax) break;
-            const int i = q + G * u;
-            if (go && i < n) {
-                const uint64_t kk = A[i];
-                col_word[s0 + i] = static_cast<uint32_t>(kk >> 32);
-                val_out[s0 + i] = static_cast<ET>(B[static_cast<uint32_t>(kk)]);
+            if (go && q + G * u < n && static_cast<unsigned>(pos[u]) < static_cast<unsigned>(n)) {
+                col_word[s0 + pos[u]] = wd[u];
+                val_out[s0 + pos[u]] = v[u];
             }
         }
         wave_lds_sync();  // the wave's slice is reused below
@@ -476,8 +470,8 @@ __global__ __launch_bounds__(kConvThreads) void from_csr_group_kernel(
         while (mids) {
             const int leader = __ffsll(static_cast<unsigned long long>(mids)) - 1;
             mids &= mids - 1;
-            sort_strip_wave<HB, WCAP, ET>(strip0 + leader / G, rows, height, bits, row_ptr, col_ind, val_in,
-                                          col_word, val_out, lds[wave], rowtab[wave], lane);
+            sort_strip_mid<HB, E, ET>(strip0 + leader / G, rows, height, bits, row_ptr, col_ind, val_in, col_word,
+                                      val_out, lds[wave], rowtab[wave], lane);
         }
     }
 }
@@ -608,33 +602,46 @@ __global__ __launch_bounds__(kConvThreads) void sort_list_wave_kernel(
     int rows, int height, int bits, const int* __restrict__ row_ptr, const int* __restrict__ col_ind,
     const ET* __restrict__ val_in, uint32_t* __restrict__ col_word, ET* __restrict__ val_out,
     const int* __restrict__ ws_count, const int* __restrict__ ws_small) {
-    __shared__ uint64_t keys[kConvWaves][2 * kWaveSortCap];
+    __shared__ uint64_t keys[kConvWaves][kWaveSortCap];
     __shared__ int rtab[kConvWaves][HB + 1];
     const int lane = lane_id();
     const int wave = uniform(static_cast<int>(threadIdx.x) / kWave);
     const int count = ws_count[0];
     const int nwaves = static_cast<int>(gridDim.x) * kConvWaves;
     for (int item = static_cast<int>(blockIdx.x) * kConvWaves + wave; item < count; item += nwaves)
-        sort_strip_wave<HB, kWaveSortCap, ET>(ws_small[item], rows, height, bits, row_ptr, col_ind, val_in, col_word,
-                                              val_out, keys[wave], rtab[wave], lane);
+        sort_strip_mid<HB, kWaveSortCap / kWave, ET>(ws_small[item], rows, height, bits, row_ptr, col_ind, val_in,
+                                                     col_word, val_out, keys[wave], rtab[wave], lane);
 }
 
-// One listed long strip of n entries by the whole 1024-thread workgroup, keys
-// in A (n entries) with B (n entries) as the second merge buffer.  Strips whose
-// rows are sorted by column are merged run by run (merge_strip_runs); the
-// others are sorted by a bitonic network in place in A, which then needs room
-// for pow2(n) <= 2n keys.  keys_global / merge_global say whether A / B lie in
-// global memory (the strip's workspace slice), whose passes then need an
-// agent-scope fence before the barrier.  Forced inline, so that each call
-// site keeps LDS buffers in the LDS address space.
+// The word (col << bits | RowInStrip) of entry i of a strip.
+template <int HB>
+__device__ inline uint32_t strip_word(const StripRows& sr, const int* __restrict__ col_ind, int bits, int i) {
+    const int r = row_in_strip<HB>(sr.myrp, sr.s0 + i, 0);
+    return (static_cast<uint32_t>(col_ind[sr.s0 + i]) << bits) | static_cast<uint32_t>(r);
+}
+
+// One listed long strip of n entries by the whole 1024-thread workgroup, in K
+// (LDS, or the strip's workspace slice of 2n 64-bit words when keys_global;
+// passes over global memory then need an agent-scope fence before the
+// barrier).  Rows sorted by column: the words sit in K as 32-bit words in
+// strip order and each entry's place in the sorted strip is its index in its
+// own row plus, for every other row, the number of that row's words below
+// its own (binary search; the words of different rows never tie).  No second
+// buffer and no passes: one barrier after the words are in.  Otherwise a
+// bitonic network over (word, position) keys in K, which needs room for
+// pow2(n) <= 2n keys.  Forced inline, so that the LDS call site keeps the LDS
+// address space.
 template <int HB, typename ET>
 __device__ __forceinline__ void sort_strip_block(const StripRows& sr, int n, int bits,
                                                  const int* __restrict__ col_ind, const ET* __restrict__ val_in,
-                                                 uint32_t* __restrict__ col_word, ET* __restrict__ val_out,
-                                                 uint64_t* A, uint64_t* B, bool keys_global, bool merge_global,
-                                                 int* rt, int tid, int wave, int lane) {
-    const uint32_t mask = (1u << bits) - 1u;
-    // Keys in order, with the canonical-row check on the way: entry i and
+                                                 uint32_t* __restrict__ col_word, ET* __restrict__ val_out, uint64_t* K,
+                                                 bool keys_global, int* rt, int tid, int wave, int lane) {
+    uint32_t* W = reinterpret_cast<uint32_t*>(K);
+    const auto sync = [keys_global] {
+        if (keys_global) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+        __syncthreads();
+    };
+    // Words in order, with the canonical-row check on the way: entry i and
     // i + 1 of one row must not descend by column.
     bool bad = false;
     for (int base = wave * kWave; base < n; base += kBlockSortThreads) {
@@ -643,43 +650,59 @@ __device__ __forceinline__ void sort_strip_block(const StripRows& sr, int n, int
         const int rn = row_in_strip<HB>(sr.myrp, sr.s0 + i + 1, 0);
         if (i < n) {
             const int c = col_ind[sr.s0 + i];
-            const uint32_t w = (static_cast<uint32_t>(c) << bits) | static_cast<uint32_t>(r);
-            A[i] = (static_cast<uint64_t>(w) << 32) | static_cast<uint32_t>(i);
+            W[i] = (static_cast<uint32_t>(c) << bits) | static_cast<uint32_t>(r);
             if (i + 1 < n && rn == r && col_ind[sr.s0 + i + 1] < c) bad = true;
         }
     }
     if (tid <= HB) rt[tid] = tid < sr.nr ? sr.myrp - sr.s0 : n;  // wave 0: lane == tid
     if (keys_global) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
-    const bool any_bad = __syncthreads_or(bad) != 0;
-    const uint64_t* res;
-    if (!any_bad) {
-        res = merge_strip_runs<HB>(A, B, n, rt, mask, tid, kBlockSortThreads, [merge_global] {
-            if (merge_global) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
-            __syncthreads();
-        });
+    if (__syncthreads_or(bad) == 0) {
+        for (int i = tid; i < n; i += kBlockSortThreads) {
+            const uint32_t w = W[i];
+            const int r = static_cast<int>(w & static_cast<uint32_t>(HB - 1));
+            int pos = i - rt[r];
+            for (int x = 0; x < HB; ++x) {
+                if (x == r) continue;
+                const int lo = rt[x];
+                int a = lo, len = rt[x + 1] - lo;
+                while (len > 0) {
+                    const int half = len >> 1;
+                    if (W[a + half] < w) {
+                        a += half + 1;
+                        len -= half + 1;
+                    } else {
+                        len = half;
+                    }
+                }
+                pos += a - lo;
+            }
+            if (static_cast<unsigned>(pos) < static_cast<unsigned>(n)) {
+                col_word[sr.s0 + pos] = w;
+                val_out[sr.s0 + pos] = val_in[sr.s0 + i];
+            }
+        }
     } else {
         const int P = pow2_at_least(n);
-        for (int i = n + tid; i < P; i += kBlockSortThreads) A[i] = ~0ull;
-        const auto sync = [keys_global] {
-            if (keys_global) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
-            __syncthreads();
-        };
+        sync();  // W is read above; the keys overwrite it
+        for (int i = tid; i < P; i += kBlockSortThreads) {
+            uint64_t key = ~0ull;
+            if (i < n) key = (static_cast<uint64_t>(strip_word<HB>(sr, col_ind, bits, i)) << 32) | static_cast<uint32_t>(i);
+            K[i] = key;
+        }
         sync();
-        bitonic_sort(A, P, tid, kBlockSortThreads, sync);
-        res = A;
-    }
-    for (int i = tid; i < n; i += kBlockSortThreads) {
-        const uint64_t kk = res[i];
-        col_word[sr.s0 + i] = static_cast<uint32_t>(kk >> 32);
-        val_out[sr.s0 + i] = val_in[sr.s0 + static_cast<int>(static_cast<uint32_t>(kk))];
+        bitonic_sort(K, P, tid, kBlockSortThreads, sync);
+        for (int i = tid; i < n; i += kBlockSortThreads) {
+            const uint64_t kk = K[i];
+            col_word[sr.s0 + i] = static_cast<uint32_t>(kk >> 32);
+            val_out[sr.s0 + i] = val_in[sr.s0 + static_cast<int>(static_cast<uint32_t>(kk))];
+        }
     }
 }
 
 // Sorted conversion of the listed long strips: one 1024-thread workgroup per
-// strip, strips taken in a grid-stride loop.  The keys live in LDS when the
-// strip fits (n <= kBlockSortCap), else in the strip's own slice of the
-// workspace [2*s0, 2*s1); the merge's second buffer is LDS when both fit
-// (n <= kBlockSortCap / 2), else that slice.
+// strip, strips taken in a grid-stride loop; the keys in LDS when the strip
+// fits (n <= kBlockSortCap), else in the strip's own slice of the workspace
+// [2*s0, 2*s1).
 template <int HB, typename ET>
 __global__ __launch_bounds__(kBlockSortThreads) void sort_list_block_kernel(
     int rows, int height, int bits, const int* __restrict__ row_ptr, const int* __restrict__ col_ind,
@@ -694,16 +717,12 @@ __global__ __launch_bounds__(kBlockSortThreads) void sort_list_block_kernel(
     for (int item = blockIdx.x; item < count; item += gridDim.x) {
         const StripRows sr = load_strip_rows(ws_big[item], rows, height, row_ptr, lane);
         const int n = sr.s1 - sr.s0;
-        uint64_t* slice = gkeys + 2 * static_cast<size_t>(sr.s0);
-        if (2 * n <= kBlockSortCap)
-            sort_strip_block<HB, ET>(sr, n, bits, col_ind, val_in, col_word, val_out, skeys, skeys + n, false,
-                                     false, rt, tid, wave, lane);
-        else if (n <= kBlockSortCap)
-            sort_strip_block<HB, ET>(sr, n, bits, col_ind, val_in, col_word, val_out, skeys, slice, false, true, rt,
-                                     tid, wave, lane);
+        if (n <= kBlockSortCap)
+            sort_strip_block<HB, ET>(sr, n, bits, col_ind, val_in, col_word, val_out, skeys, false, rt, tid, wave,
+                                     lane);
         else
-            sort_strip_block<HB, ET>(sr, n, bits, col_ind, val_in, col_word, val_out, slice, slice + n, true, true,
-                                     rt, tid, wave, lane);
+            sort_strip_block<HB, ET>(sr, n, bits, col_ind, val_in, col_word, val_out,
+                                     gkeys + 2 * static_cast<size_t>(sr.s0), true, rt, tid, wave, lane);
         __syncthreads();  // the next item reuses skeys and rt
     }
 }
