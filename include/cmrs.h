@@ -111,8 +111,9 @@ int32_t cmrs_num_strips(int32_t rows, int32_t height);
 int32_t cmrs_bits_for_height(int32_t height);
 
 /* Bytes of workspace cmrs_from_csr needs: 0 without CMRS_SORT; with it,
- * room for the strips that do not fit one workgroup's LDS (a list of their
- * indices and a global sort buffer).  Host only. */
+ * two lists of the strips too long to be sorted inside the conversion kernel
+ * and a global sort buffer for strips that do not fit one workgroup's LDS.
+ * Host only. */
 size_t cmrs_from_csr_workspace(int32_t rows, int32_t nnz, int32_t height, uint32_t flags);
 
 /*
