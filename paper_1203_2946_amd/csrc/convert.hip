@@ -7,9 +7,12 @@
 //   order (Sec. 4, fourth optimisation).
 // CMRS -> CSR is the inverse: per-row counts inside a strip give RowPtr (no
 // global scan is needed, a strip's entries are exactly its rows' entries), and
-// a stable scatter by RowInStrip restores row order.
+// a stable scatter by RowInStrip restores row order.  One wave takes the
+// whole strips of 32 consecutive rows and streams their entries (contiguous)
+// with coalesced loads, counting, then scattering; at height 1 the
+// conversion is a plain copy.
 //
-// Work split.  The main kernels give each strip a group of G lanes (64/G
+// Work split of CSR -> CMRS.  The main kernel gives each strip a group of G lanes (64/G
 // strips per wave) and each lane up to E = 8 entries, all loaded before any is
 // used, so a wave keeps 64*E entries of traffic in flight.  The row of
 // an entry comes from a binary search over the strip's row pointers, which sit
@@ -250,78 +253,6 @@ __device__ inline void sort_strip_mid(int strip, int rows, int height, int bits,
     wave_lds_sync();
 }
 
-// CMRS -> CSR of one strip by the whole wave (two passes over the strip, 4
-// loads per lane in flight).
-template <int HB, typename ET>
-__device__ inline void to_csr_strip_wave(int strip, int rows, int strips, int height, int bits,
-                                         const int* __restrict__ strip_ptr, const uint32_t* __restrict__ word,
-                                         const ET* __restrict__ val, int* __restrict__ row_ptr,
-                                         int* __restrict__ col_ind, ET* __restrict__ val_out, int lane) {
-    constexpr int U = 4;
-    const int r0 = strip * height;
-    const int nr = min(height, rows - r0);
-    const int s0 = strip_ptr[strip], s1 = strip_ptr[strip + 1];
-    const uint32_t mask = (1u << bits) - 1u;
-    // Pass 1: lane t counts the entries whose RowInStrip is t.
-    int cnt = 0;
-    for (int b0 = s0; b0 < s1; b0 += U * kWave) {
-        uint32_t r[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = b0 + u * kWave + lane;
-            r[u] = e < s1 ? (word[e] & mask) : 0xffffffffu;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-#pragma unroll 4
-            for (int t = 0; t < HB; ++t) {
-                const uint64_t m = ballot(r[u] == static_cast<uint32_t>(t));
-                if (lane == t) cnt += __popcll(m);
-            }
-        }
-    }
-    // Exclusive prefix over lanes: the CSR position of each row's first entry.
-    int incl = cnt;
-#pragma unroll
-    for (int off = 1; off < HB; off <<= 1) {
-        const int v = __shfl_up(incl, off);
-        if (lane >= off) incl += v;
-    }
-    const int start = s0 + incl - cnt;
-    if (lane < nr) row_ptr[r0 + lane] = start;
-    if (strip == strips - 1 && lane == 0) row_ptr[rows] = s1;
-    // Pass 2: stable scatter; lane t tracks the next free slot of row t.
-    int next = start;
-    for (int b0 = s0; b0 < s1; b0 += U * kWave) {
-        uint32_t w[U];
-        ET v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = b0 + u * kWave + lane;
-            w[u] = e < s1 ? word[e] : 0u;
-            v[u] = e < s1 ? val[e] : ET(0);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = b0 + u * kWave + lane;
-            const bool act = e < s1;
-            const uint32_t r = act ? (w[u] & mask) : 0xffffffffu;
-            int pos = 0;
-#pragma unroll 4
-            for (int t = 0; t < HB; ++t) {
-                const uint64_t m = ballot(r == static_cast<uint32_t>(t));
-                const int base_t = __shfl(next, t);
-                if (r == static_cast<uint32_t>(t)) pos = base_t + __popcll(m & lanemask_lt());
-                if (lane == t) next += __popcll(m);
-            }
-            if (act && r < static_cast<uint32_t>(nr)) {
-                col_ind[pos] = static_cast<int>(w[u] >> bits);
-                val_out[pos] = v[u];
-            }
-        }
-    }
-}
-
 // ------------------------------------------------------------------ group kernels
 
 __device__ inline uint64_t group_mask(int gbase, int G) {
@@ -476,120 +407,210 @@ __global__ __launch_bounds__(kConvThreads) __attribute__((amdgpu_waves_per_eu(8)
     }
 }
 
-// CMRS -> CSR for strips of at most G*E entries, G lanes per strip;
-// longer strips by the whole wave afterwards.
-template <int HB, int G, int E, typename ET>
-__global__ __launch_bounds__(kConvThreads) void to_csr_group_kernel(
-    int rows, int strips, int height, int bits, const int* __restrict__ strip_ptr,
+// CMRS -> CSR at height 1: every strip is one row, so RowPtr is StripPtr and
+// every entry keeps its place (column = word >> bits); a plain coalesced
+// stream.  (A word with a non-zero RowInStrip is invalid input at height 1;
+// it is copied like the others.)
+template <typename ET>
+__global__ __launch_bounds__(256) void to_csr_h1_kernel(int rows, int nnz, int bits, const int* __restrict__ strip_ptr,
+                                                        const uint32_t* __restrict__ word, const ET* __restrict__ val,
+                                                        int* __restrict__ row_ptr, int* __restrict__ col_ind,
+                                                        ET* __restrict__ val_out) {
+    constexpr int U = 4;
+    const int64_t nthreads = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    const int64_t tid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    for (int64_t i = tid; i <= rows; i += nthreads) row_ptr[i] = strip_ptr[i];
+    for (int64_t b0 = static_cast<int64_t>(blockIdx.x) * blockDim.x * U; b0 < nnz; b0 += nthreads * U) {
+        uint32_t w[U];
+        ET v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t j = b0 + u * blockDim.x + threadIdx.x;
+            w[u] = j < nnz ? word[j] : 0u;
+            v[u] = j < nnz ? val[j] : ET(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t j = b0 + u * blockDim.x + threadIdx.x;
+            if (j < nnz) {
+                col_ind[j] = static_cast<int>(w[u] >> bits);
+                val_out[j] = v[u];
+            }
+        }
+    }
+}
+
+// Strip of every lane's entry in one round of a wave's run of whole strips.
+// Lane t <= nsw holds StripPtr[S + t] (INT_MAX past that); `tc` (uniform)
+// enters as the last strip whose pointer is <= the round's first entry and
+// leaves as that of the round's last entry `lim`, so the rounds of a run step
+// through its strip pointers once, whatever the strip lengths.  Empty strips
+// are passed over because their pointer repeats.
+__device__ inline int round_strip(int myp, int j, int lim, int& tc) {
+    int t = tc;
+    for (;;) {
+        const int nx = __builtin_amdgcn_readlane(myp, tc + 1);
+        if (nx > lim) break;
+        if (j >= nx) t = tc + 1;
+        ++tc;
+    }
+    return t;
+}
+
+// Key of an entry of strip t of the run: t*height + RowInStrip, the row's
+// offset from the run's first row; -1 for a word whose RowInStrip names no
+// row of its strip (the entry is then neither counted nor written).
+__device__ inline int run_row_key(int t, uint32_t r, int height, int nrow) {
+    const int key = t * height + static_cast<int>(r);
+    return (r < static_cast<uint32_t>(height) && key < nrow) ? key : -1;
+}
+
+// Rows per wave of the CMRS -> CSR kernel: lane k < kRunRows owns row k of
+// the wave's run, and row keys fit in kRunKeyBits bits.
+constexpr int kRunRows = 32;
+constexpr int kRunKeyBits = 5;
+
+// Lanes of `valid` whose key (< kRunRows) equals k, from kb[b] = ballot of bit
+// b of every lane's key: a match over the wave without a loop over key values.
+__device__ inline uint64_t key_match(int k, uint64_t valid, const uint64_t (&kb)[kRunKeyBits]) {
+    uint64_t m = valid;
+#pragma unroll
+    for (int b = 0; b < kRunKeyBits; ++b) m &= ((k >> b) & 1) ? kb[b] : ~kb[b];
+    return m;
+}
+
+// One round of 64 consecutive entries [b, b + 64) of a run: every lane's row
+// key (-1: no entry or an invalid word), its key ballots and the valid mask.
+struct RunRound {
+    int key;
+    uint64_t valid;
+    uint64_t kb[kRunKeyBits];
+};
+
+__device__ inline RunRound run_round(int myp, int b, int e1, uint32_t w, uint32_t mask, int height, int nrow, int& tc) {
+    RunRound rr;
+    const int j = b + lane_id();
+    const int t = round_strip(myp, j, min(b + kWave, e1) - 1, tc);
+    rr.key = j < e1 ? run_row_key(t, w & mask, height, nrow) : -1;
+#pragma unroll
+    for (int k = 0; k < kRunKeyBits; ++k) rr.kb[k] = ballot(rr.key >= 0 && ((rr.key >> k) & 1));
+    rr.valid = ballot(rr.key >= 0);
+    return rr;
+}
+
+// CMRS -> CSR with one wave per run of `ns` whole strips (ns*height <=
+// kRunRows consecutive rows, lane k owning row k of the run).  The run's
+// entries are contiguous, so the wave streams them 64 at a time with
+// coalesced loads whatever the strip lengths.  Pass 1 counts the entries of
+// every row (the rows' CSR starts are then a prefix sum over the lanes); pass
+// 2 scatters each entry to its row's start plus its rank, the number of
+// earlier entries of the same row (earlier rounds: a per-row counter; this
+// round: lanes below it with the same key).  The scatter keeps strip order
+// inside every row, the stable order of the inverse conversion.  A run of at
+// most FIT entries is loaded once and both passes work on the registers;
+// longer runs are read twice.
+template <typename ET>
+__global__ __launch_bounds__(kConvThreads) void to_csr_rows_kernel(
+    int rows, int strips, int height, int bits, int ns, const int* __restrict__ strip_ptr,
     const uint32_t* __restrict__ word, const ET* __restrict__ val, int* __restrict__ row_ptr,
     int* __restrict__ col_ind, ET* __restrict__ val_out) {
-    static_assert(G >= HB && G <= kWave && G >= 2, "group width");
-    constexpr int NG = kWave / G;
-    constexpr int CAP = G * E;
+    constexpr int UF = 12, U = 8, FIT = UF * kWave;
     const int lane = lane_id();
     const int wave = uniform(static_cast<int>(threadIdx.x) / kWave);
-    const int strip0 = (xcd_logical_block(blockIdx.x, gridDim.x) * kConvWaves + wave) * NG;
-    if (strip0 >= strips) return;
-    const int g = lane / G, q = lane % G, gbase = g * G;
-    const int strip = strip0 + g;
-    const bool valid = strip < strips;
-    const int s0 = valid ? strip_ptr[strip] : 0;
-    const int s1 = valid ? strip_ptr[strip + 1] : 0;
-    const int n = s1 - s0;
-    const int r0 = strip * height;
-    const int nr = valid ? min(height, rows - r0) : 0;
-    const bool is_long = valid && n > CAP;
-    const bool go = valid && !is_long;
+    const int S = (xcd_logical_block(blockIdx.x, gridDim.x) * kConvWaves + wave) * ns;
+    if (S >= strips) return;
+    const int nsw = min(ns, strips - S);
+    const int myp = lane <= nsw ? strip_ptr[S + lane] : INT_MAX;
+    const int e0 = uniform(__shfl(myp, 0)), e1 = uniform(__shfl(myp, nsw));
+    const int r0 = S * height;
+    const int nrow = min(nsw * height, rows - r0);
     const uint32_t mask = (1u << bits) - 1u;
-    const uint64_t gm = group_mask(gbase, G);
     const uint64_t lt = lanemask_lt();
 
-    const int umax = used_slots<G>(go ? n : 0);
-    uint32_t w[E], r[E];
-    ET v[E];
-    int rank[E];
-#pragma unroll
-    for (int u = 0; u < E; ++u) {
-        w[u] = 0u;
-        v[u] = ET(0);
-        r[u] = 0xffffffffu;
-        rank[u] = 0;
-        if (u < umax) {
-            const int j = s0 + q + G * u;
-            if (go && j < s1) {
-                w[u] = word[j];
-                v[u] = val[j];
-                r[u] = w[u] & mask;
-            }
-        }
-    }
-    int start;  // lane gbase + rr (rr < HB): CSR position of the first entry of row rr
-    if constexpr (G == kWave && HB <= 8) {
-        // One strip per wave: the per-row counters are wave-uniform.
-        int running[HB];
-#pragma unroll
-        for (int rr = 0; rr < HB; ++rr) running[rr] = 0;
-#pragma unroll
-        for (int u = 0; u < E; ++u) {
-            if (u >= umax) break;
-#pragma unroll
-            for (int rr = 0; rr < HB; ++rr) {
-                const uint64_t m = ballot(r[u] == static_cast<uint32_t>(rr));
-                if (r[u] == static_cast<uint32_t>(rr)) rank[u] = running[rr] + __popcll(m & lt);
-                running[rr] += __popcll(m);
-            }
-        }
-        int acc = s0;
-        start = s0;
-#pragma unroll
-        for (int rr = 0; rr < HB; ++rr) {
-            if (q == rr) start = acc;
-            acc += running[rr];
-        }
-    } else {
-        int running = 0;  // lane gbase + rr: entries of RowInStrip rr seen so far
-#pragma unroll
-        for (int u = 0; u < E; ++u) {
-            if (u >= umax) break;
-#pragma unroll 1
-            for (int rr = 0; rr < HB; ++rr) {
-                const uint64_t m = ballot(r[u] == static_cast<uint32_t>(rr)) & gm;
-                const int before = __shfl(running, gbase + rr);
-                if (r[u] == static_cast<uint32_t>(rr)) rank[u] = before + __popcll(m & lt);
-                if (q == rr) running += __popcll(m);
-            }
-        }
-        // Exclusive prefix of the per-row counts inside the group.
-        const int cnt = q < HB ? running : 0;
+    auto row_starts = [&](int cnt) {
         int incl = cnt;
 #pragma unroll
-        for (int off = 1; off < HB; off <<= 1) {
-            const int sv = __shfl_up(incl, off, G);
-            if (q >= off) incl += sv;
+        for (int off = 1; off < kRunRows; off <<= 1) {
+            const int v = __shfl_up(incl, off);
+            if (lane >= off) incl += v;
         }
-        start = s0 + incl - cnt;
-    }
-    if (go && q < nr) row_ptr[r0 + q] = start;
-    if (valid && strip == strips - 1 && q == 0) row_ptr[rows] = s1;
+        const int start = e0 + incl - cnt;
+        if (lane < nrow) row_ptr[r0 + lane] = start;
+        if (S + nsw == strips && lane == 0) row_ptr[rows] = e1;
+        return start;
+    };
+    // Scatter of one round; `next` (lane k): CSR position of the next entry of row k.
+    auto scatter = [&](const RunRound& rr, uint32_t w, ET v, int& next) {
+        const int src = rr.key >= 0 ? rr.key : 0;
+        const int pos = __shfl(next, src) + __popcll(key_match(src, rr.valid, rr.kb) & lt);
+        // pos lies in [e0, e1) by construction; the check keeps a corrupt
+        // strip from writing outside its run.
+        if (rr.key >= 0 && static_cast<unsigned>(pos - e0) < static_cast<unsigned>(e1 - e0)) {
+            col_ind[pos] = static_cast<int>(w >> bits);
+            val_out[pos] = v;
+        }
+        next += __popcll(key_match(lane, rr.valid, rr.kb));
+    };
+
+    if (e1 - e0 <= FIT) {
+        uint32_t w[UF];
+        ET v[UF];
 #pragma unroll
-    for (int u = 0; u < E; ++u) {
-        if (u >= umax) break;
-        const int j = s0 + q + G * u;
-        const int base = __shfl(start, gbase + static_cast<int>(r[u] & (HB - 1)));
-        // r < nr holds for every valid word; the guard keeps an invalid one from
-        // writing outside this strip's range [s0, s1).
-        if (go && j < s1 && r[u] < static_cast<uint32_t>(nr)) {
-            const int p = base + rank[u];
-            col_ind[p] = static_cast<int>(w[u] >> bits);
-            val_out[p] = v[u];
+        for (int u = 0; u < UF; ++u) {
+            const int j = e0 + u * kWave + lane;
+            w[u] = j < e1 ? word[j] : 0u;
+            v[u] = j < e1 ? val[j] : ET(0);
+        }
+        int cnt = 0, tc = 0;
+#pragma unroll
+        for (int u = 0; u < UF; ++u) {
+            if (e0 + u * kWave >= e1) break;
+            const RunRound rr = run_round(myp, e0 + u * kWave, e1, w[u], mask, height, nrow, tc);
+            cnt += __popcll(key_match(lane, rr.valid, rr.kb));
+        }
+        int next = row_starts(cnt);
+        tc = 0;
+#pragma unroll
+        for (int u = 0; u < UF; ++u) {
+            if (e0 + u * kWave >= e1) break;
+            const RunRound rr = run_round(myp, e0 + u * kWave, e1, w[u], mask, height, nrow, tc);
+            scatter(rr, w[u], v[u], next);
+        }
+        return;
+    }
+
+    int cnt = 0, tc = 0;
+    for (int b0 = e0; b0 < e1; b0 += U * kWave) {
+        uint32_t w[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = b0 + u * kWave + lane;
+            w[u] = j < e1 ? word[j] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (b0 + u * kWave >= e1) break;
+            const RunRound rr = run_round(myp, b0 + u * kWave, e1, w[u], mask, height, nrow, tc);
+            cnt += __popcll(key_match(lane, rr.valid, rr.kb));
         }
     }
-    uint64_t longs = ballot(is_long && q == 0);
-    while (longs) {
-        const int leader = __ffsll(static_cast<unsigned long long>(longs)) - 1;
-        longs &= longs - 1;
-        to_csr_strip_wave<HB, ET>(strip0 + leader / G, rows, strips, height, bits, strip_ptr, word, val, row_ptr,
-                                  col_ind, val_out, lane);
+    int next = row_starts(cnt);
+    tc = 0;
+    for (int b0 = e0; b0 < e1; b0 += U * kWave) {
+        uint32_t w[U];
+        ET v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = b0 + u * kWave + lane;
+            w[u] = j < e1 ? word[j] : 0u;
+            v[u] = j < e1 ? val[j] : ET(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (b0 + u * kWave >= e1) break;
+            const RunRound rr = run_round(myp, b0 + u * kWave, e1, w[u], mask, height, nrow, tc);
+            scatter(rr, w[u], v[u], next);
+        }
     }
 }
 
@@ -818,46 +839,26 @@ hipError_t from_csr_typed(const Conv& cv, uint32_t flags, const int* row_ptr, co
     }
 }
 
-template <int G, int E, int HB, typename ET>
-hipError_t to_csr_g(const cmrs_mat_t* A, int strips, int* row_ptr, int* col_ind, void* val_out, hipStream_t stream) {
-    constexpr int NG = kWave / G;
-    const int waves = (strips + NG - 1) / NG;
-    const int blocks = (waves + kConvWaves - 1) / kConvWaves;
-    hipLaunchKernelGGL((to_csr_group_kernel<HB, G, E, ET>), dim3(blocks), dim3(kConvThreads), 0, stream, A->rows,
-                       strips, A->height, A->bits, A->strip_ptr, A->col_word, static_cast<const ET*>(A->val),
-                       row_ptr, col_ind, static_cast<ET*>(val_out));
-    return hipGetLastError();
-}
-
-template <int HB, typename ET>
-hipError_t to_csr_hb(const cmrs_mat_t* A, int* row_ptr, int* col_ind, void* val_out, hipStream_t stream) {
-    const int strips = (A->rows + A->height - 1) / A->height;
-    const ConvShape sh = conv_shape(A->nnz, strips, HB);
-#define CMRS_TO_G(GG, EE)                                                                         \
-    if constexpr (GG >= HB) {                                                                     \
-        if (sh.g == GG && sh.e == EE)                                                             \
-            return to_csr_g<GG, EE, HB, ET>(A, strips, row_ptr, col_ind, val_out, stream);        \
-    }
-    CMRS_TO_G(2, 8)
-    CMRS_TO_G(4, 8)
-    CMRS_TO_G(8, 8)
-    CMRS_TO_G(16, 8)
-    CMRS_TO_G(32, 8)
-    CMRS_TO_G(64, 8)
-#undef CMRS_TO_G
-    return hipErrorInvalidValue;
-}
-
 template <typename ET>
 hipError_t to_csr_typed(const cmrs_mat_t* A, int* row_ptr, int* col_ind, void* val_out, hipStream_t stream) {
-    switch (next_pow2(A->height)) {
-        case 1: return to_csr_hb<1, ET>(A, row_ptr, col_ind, val_out, stream);
-        case 2: return to_csr_hb<2, ET>(A, row_ptr, col_ind, val_out, stream);
-        case 4: return to_csr_hb<4, ET>(A, row_ptr, col_ind, val_out, stream);
-        case 8: return to_csr_hb<8, ET>(A, row_ptr, col_ind, val_out, stream);
-        case 16: return to_csr_hb<16, ET>(A, row_ptr, col_ind, val_out, stream);
-        default: return to_csr_hb<32, ET>(A, row_ptr, col_ind, val_out, stream);
+    if (A->height == 1) {
+        const int64_t work = static_cast<int64_t>(A->nnz > A->rows + 1 ? A->nnz : A->rows + 1);
+        const int64_t want = (work + 1023) / 1024;
+        const int blocks = static_cast<int>(want < 4096 ? want : 4096);
+        hipLaunchKernelGGL((to_csr_h1_kernel<ET>), dim3(blocks), dim3(256), 0, stream, A->rows, A->nnz, A->bits,
+                           A->strip_ptr, A->col_word, static_cast<const ET*>(A->val), row_ptr, col_ind,
+                           static_cast<ET*>(val_out));
+        return hipGetLastError();
     }
+    const int strips = (A->rows + A->height - 1) / A->height;
+    // Whole strips per wave: as many as fit in kRunRows rows (height <= 32).
+    const int ns = kRunRows / A->height;
+    const int waves = (strips + ns - 1) / ns;
+    const int blocks = (waves + kConvWaves - 1) / kConvWaves;
+    hipLaunchKernelGGL((to_csr_rows_kernel<ET>), dim3(blocks), dim3(kConvThreads), 0, stream, A->rows, strips,
+                       A->height, A->bits, ns, A->strip_ptr, A->col_word, static_cast<const ET*>(A->val), row_ptr,
+                       col_ind, static_cast<ET*>(val_out));
+    return hipGetLastError();
 }
 
 }  // namespace
