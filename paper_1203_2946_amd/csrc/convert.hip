@@ -12,11 +12,15 @@
 // with coalesced loads, counting, then scattering; at height 1 the
 // conversion is a plain copy.
 //
-// Work split of CSR -> CMRS.  The main kernel gives each strip a group of G lanes (64/G
-// strips per wave) and each lane up to E = 8 entries, all loaded before any is
-// used, so a wave keeps 64*E entries of traffic in flight.  The row of
-// an entry comes from a binary search over the strip's row pointers, which sit
-// one per lane of the group (cross-lane reads, no memory traffic).
+// Work split of CSR -> CMRS.  Without the reorder, entries keep their
+// places: one wave takes the whole strips of 32 consecutive rows and streams
+// their entries with coalesced loads, stepping through the row pointers to
+// find each entry's row.  With the reorder, the main kernel gives each strip a
+// group of G lanes (64/G strips per wave) and each lane up to E = 8 entries,
+// all loaded before any is used, so a wave keeps 64*E entries of traffic in
+// flight.  The row of an entry comes from a binary search over the strip's row
+// pointers, which sit one per lane of the group (cross-lane reads, no memory
+// traffic).
 //
 // Reorder: a strip of canonical CSR is `height` runs (its rows) that are
 // already sorted by column, and within a strip (column, RowInStrip) order is
@@ -102,35 +106,6 @@ __device__ inline void bitonic_sort(uint64_t* k, int P, int tid, int nthreads, S
 }
 
 // ------------------------------------------------------------------ whole-wave paths
-
-// Unsorted conversion of one strip by the whole wave, 8 loads per lane in
-// flight.
-template <int HB, typename ET>
-__device__ inline void pack_strip_wave(int strip, int rows, int height, int bits, const int* __restrict__ row_ptr,
-                                       const int* col_ind, const ET* val_in, uint32_t* col_word, ET* val_out,
-                                       int copy_val, int lane) {
-    constexpr int U = 8;
-    const StripRows sr = load_strip_rows(strip, rows, height, row_ptr, lane);
-    for (int base = sr.s0; base < sr.s1; base += U * kWave) {
-        int c[U];
-        ET v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = base + u * kWave + lane;
-            c[u] = e < sr.s1 ? col_ind[e] : 0;
-            v[u] = (e < sr.s1 && copy_val) ? val_in[e] : ET(0);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = base + u * kWave + lane;
-            const int r = row_in_strip<HB>(sr.myrp, e, 0);
-            if (e < sr.s1) {
-                col_word[e] = (static_cast<uint32_t>(c[u]) << bits) | static_cast<uint32_t>(r);
-                if (copy_val) val_out[e] = v[u];
-            }
-        }
-    }
-}
 
 // Merge of the row runs of strips held in registers, G lanes per strip, slot u
 // of lane q holding entry q + G*u: words (col << bits | RowInStrip) in wd and
@@ -269,24 +244,23 @@ __device__ inline int used_slots(int n) {
     return uniform((m + G - 1) / G);
 }
 
-// CSR -> CMRS for strips of at most G*E entries, G lanes per strip.
-// Writes strip_ptr too.  Unsorted: longer strips are packed by the whole
-// wave afterwards.  Sorted: longer strips of at most kWave*E entries and
-// strips with unsorted rows are sorted by the whole wave afterwards in the
+// CSR -> CMRS with the reorder, for strips of at most G*E entries, G lanes
+// per strip.  Writes strip_ptr too.  Longer strips of at most kWave*E entries
+// and strips with unsorted rows are sorted by the whole wave afterwards in the
 // wave's LDS slice; still longer ones go to the workspace lists
 // (ws_count[0] / ws_small: at most kWaveSortCap entries; ws_count[1] /
-// ws_big: longer).  col_word may alias col_ind and val_out may alias val_in
-// only when unsorted.
-template <int HB, int G, int E, bool SORT, typename ET>
+// ws_big: longer).  No output may alias an input.
+template <int HB, int G, int E, typename ET>
 __global__ __launch_bounds__(kConvThreads) __attribute__((amdgpu_waves_per_eu(8))) void from_csr_group_kernel(
-    int rows, int strips, int height, int bits, int nnz, const int* __restrict__ row_ptr, const int* col_ind,
-    const ET* val_in, int* __restrict__ strip_ptr, uint32_t* col_word, ET* val_out, int copy_val,
-    int* __restrict__ ws_count, int* __restrict__ ws_small, int* __restrict__ ws_big) {
+    int rows, int strips, int height, int bits, int nnz, const int* __restrict__ row_ptr,
+    const int* __restrict__ col_ind, const ET* __restrict__ val_in, int* __restrict__ strip_ptr,
+    uint32_t* __restrict__ col_word, ET* __restrict__ val_out, int* __restrict__ ws_count,
+    int* __restrict__ ws_small, int* __restrict__ ws_big) {
     static_assert(G >= HB && G <= kWave && G >= 2, "group width");
     constexpr int NG = kWave / G;
     constexpr int CAP = G * E;
-    __shared__ uint64_t lds[SORT ? kConvWaves : 1][SORT ? kWave * E : 1];
-    __shared__ int rowtab[SORT ? kConvWaves : 1][SORT ? NG * (HB + 1) : 1];
+    __shared__ uint64_t lds[kConvWaves][kWave * E];
+    __shared__ int rowtab[kConvWaves][NG * (HB + 1)];
     const int lane = lane_id();
     const int wave = uniform(static_cast<int>(threadIdx.x) / kWave);
     const int strip0 = (xcd_logical_block(blockIdx.x, gridDim.x) * kConvWaves + wave) * NG;
@@ -326,24 +300,7 @@ __global__ __launch_bounds__(kConvThreads) __attribute__((amdgpu_waves_per_eu(8)
         }
     }
 
-    if constexpr (!SORT) {
-#pragma unroll
-        for (int u = 0; u < E; ++u) {
-            const int j = s0 + q + G * u;
-            if (u < umax && valid && !special && j < s1) {
-                col_word[j] = (static_cast<uint32_t>(c[u]) << bits) | static_cast<uint32_t>(t[u]);
-                if (copy_val) val_out[j] = v[u];
-            }
-        }
-        uint64_t longs = ballot(special && q == 0);
-        while (longs) {
-            const int leader = __ffsll(static_cast<unsigned long long>(longs)) - 1;
-            longs &= longs - 1;
-            pack_strip_wave<HB, ET>(strip0 + leader / G, rows, height, bits, row_ptr, col_ind, val_in, col_word,
-                                    val_out, copy_val, lane);
-        }
-        return;
-    } else {
+    {
         // Words of every strip the group holds in LDS by place, and the
         // strip-relative row pointers of rows 0..HB (rows past the strip: n).
         const bool fits = valid && !special;
@@ -614,6 +571,57 @@ __global__ __launch_bounds__(kConvThreads) void to_csr_rows_kernel(
     }
 }
 
+// CSR -> CMRS without the reorder, one wave per run of `ns` whole strips
+// (ns*height <= kRunRows consecutive rows); lane k <= nrow holds RowPtr of
+// row k of the run.  Entries keep their places, so the wave streams the run's
+// (contiguous) entries 64 at a time with coalesced loads: the row of every
+// entry comes from stepping through the run's row pointers (`round_strip`),
+// and word = col << bits | (row mod height).  Writes the strip pointers too.
+// col_word may alias col_ind and val_out may alias val_in (each entry is read
+// and written by the same lane).
+template <typename ET>
+__global__ __launch_bounds__(kConvThreads) void from_csr_rows_kernel(
+    int rows, int strips, int height, int bits, int nnz, int ns, const int* __restrict__ row_ptr,
+    const int* col_ind, const ET* val_in, int* __restrict__ strip_ptr, uint32_t* col_word, ET* val_out,
+    int copy_val) {
+    constexpr int U = 8;
+    const int lane = lane_id();
+    const int wave = uniform(static_cast<int>(threadIdx.x) / kWave);
+    const int S = (xcd_logical_block(blockIdx.x, gridDim.x) * kConvWaves + wave) * ns;
+    if (S >= strips) return;
+    const int nsw = min(ns, strips - S);
+    const int r0 = S * height;
+    const int nrow = min(nsw * height, rows - r0);
+    const int myrp = lane <= nrow ? row_ptr[r0 + lane] : INT_MAX;
+    const int e0 = uniform(__shfl(myrp, 0)), e1 = uniform(__shfl(myrp, nrow));
+    const int sfirst = __shfl(myrp, min(lane * height, kRunRows));  // first entry of strip S + lane
+    if (lane < nsw) strip_ptr[S + lane] = sfirst;
+    if (S + nsw == strips && lane == 0) strip_ptr[strips] = nnz;
+    const bool pow2 = (height & (height - 1)) == 0;
+    int tc = 0;
+    for (int b0 = e0; b0 < e1; b0 += U * kWave) {
+        int c[U];
+        ET v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = b0 + u * kWave + lane;
+            c[u] = j < e1 ? col_ind[j] : 0;
+            v[u] = j < e1 ? val_in[j] : ET(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (b0 + u * kWave >= e1) break;
+            const int j = b0 + u * kWave + lane;
+            const int k = round_strip(myrp, j, min(b0 + u * kWave + kWave, e1) - 1, tc);
+            const int r = pow2 ? (k & (height - 1)) : k % height;
+            if (j < e1) {
+                col_word[j] = (static_cast<uint32_t>(c[u]) << bits) | static_cast<uint32_t>(r);
+                if (copy_val) val_out[j] = v[u];
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ list kernels
 
 // Sorted conversion of the listed strips of at most kWaveSortCap entries: one
@@ -772,19 +780,13 @@ struct Conv {
 };
 
 template <int G, int E, int HB, typename ET>
-hipError_t from_csr_g(const Conv& cv, uint32_t flags, const int* row_ptr, const int* col_ind, const void* val_in,
+hipError_t from_csr_g(const Conv& cv, const int* row_ptr, const int* col_ind, const void* val_in,
                       int* strip_ptr, uint32_t* col_word, void* val_out, void* workspace, hipStream_t stream) {
     constexpr int NG = kWave / G;
     const int waves = (cv.strips + NG - 1) / NG;
     const int blocks = (waves + kConvWaves - 1) / kConvWaves;
     const auto* vin = static_cast<const ET*>(val_in);
     auto* vout = static_cast<ET*>(val_out);
-    if (!(flags & CMRS_SORT)) {
-        hipLaunchKernelGGL((from_csr_group_kernel<HB, G, E, false, ET>), dim3(blocks), dim3(kConvThreads), 0, stream,
-                           cv.rows, cv.strips, cv.height, cv.bits, cv.nnz, row_ptr, col_ind, vin, strip_ptr, col_word,
-                           vout, val_out != val_in ? 1 : 0, nullptr, nullptr, nullptr);
-        return hipGetLastError();
-    }
     const FromCsrWorkspaceLayout L = from_csr_workspace_layout(cv.rows, cv.nnz, cv.height);
     auto* ws = static_cast<char*>(workspace);
     int* ws_count = reinterpret_cast<int*>(ws);
@@ -792,9 +794,9 @@ hipError_t from_csr_g(const Conv& cv, uint32_t flags, const int* row_ptr, const 
     int* ws_big = reinterpret_cast<int*>(ws + L.big_off);
     auto* gkeys = reinterpret_cast<uint64_t*>(ws + L.global_off);
     hipLaunchKernelGGL(set_ints_kernel, dim3(1), dim3(64), 0, stream, ws_count, 2, 0);
-    hipLaunchKernelGGL((from_csr_group_kernel<HB, G, E, true, ET>), dim3(blocks), dim3(kConvThreads), 0, stream,
+    hipLaunchKernelGGL((from_csr_group_kernel<HB, G, E, ET>), dim3(blocks), dim3(kConvThreads), 0, stream,
                        cv.rows, cv.strips, cv.height, cv.bits, cv.nnz, row_ptr, col_ind, vin, strip_ptr, col_word,
-                       vout, 1, ws_count, ws_small, ws_big);
+                       vout, ws_count, ws_small, ws_big);
     const size_t small_blocks = (L.small_cap + kConvWaves - 1) / kConvWaves;
     const int g1 = static_cast<int>(small_blocks < 1024 ? small_blocks : 1024);
     hipLaunchKernelGGL((sort_list_wave_kernel<HB, ET>), dim3(g1), dim3(kConvThreads), 0, stream, cv.rows, cv.height,
@@ -806,13 +808,13 @@ hipError_t from_csr_g(const Conv& cv, uint32_t flags, const int* row_ptr, const 
 }
 
 template <int HB, typename ET>
-hipError_t from_csr_hb(const Conv& cv, uint32_t flags, const int* row_ptr, const int* col_ind, const void* val_in,
+hipError_t from_csr_hb(const Conv& cv, const int* row_ptr, const int* col_ind, const void* val_in,
                        int* strip_ptr, uint32_t* col_word, void* val_out, void* workspace, hipStream_t stream) {
     const ConvShape sh = conv_shape(cv.nnz, cv.strips, HB);
 #define CMRS_FROM_G(GG, EE)                                                                                      \
     if constexpr (GG >= HB) {                                                                                    \
         if (sh.g == GG && sh.e == EE)                                                                            \
-            return from_csr_g<GG, EE, HB, ET>(cv, flags, row_ptr, col_ind, val_in, strip_ptr, col_word, val_out, \
+            return from_csr_g<GG, EE, HB, ET>(cv, row_ptr, col_ind, val_in, strip_ptr, col_word, val_out, \
                                               workspace, stream);                                                \
     }
     CMRS_FROM_G(2, 8)
@@ -829,13 +831,22 @@ template <typename ET>
 hipError_t from_csr_typed(const Conv& cv, uint32_t flags, const int* row_ptr, const int* col_ind,
                           const void* val_in, int* strip_ptr, uint32_t* col_word, void* val_out, void* workspace,
                           hipStream_t stream) {
+    if (!(flags & CMRS_SORT)) {
+        const int ns = kRunRows / cv.height;
+        const int waves = (cv.strips + ns - 1) / ns;
+        const int blocks = (waves + kConvWaves - 1) / kConvWaves;
+        hipLaunchKernelGGL((from_csr_rows_kernel<ET>), dim3(blocks), dim3(kConvThreads), 0, stream, cv.rows,
+                           cv.strips, cv.height, cv.bits, cv.nnz, ns, row_ptr, col_ind, static_cast<const ET*>(val_in),
+                           strip_ptr, col_word, static_cast<ET*>(val_out), val_out != val_in ? 1 : 0);
+        return hipGetLastError();
+    }
     switch (next_pow2(cv.height)) {
-        case 1: return from_csr_hb<1, ET>(cv, flags, row_ptr, col_ind, val_in, strip_ptr, col_word, val_out, workspace, stream);
-        case 2: return from_csr_hb<2, ET>(cv, flags, row_ptr, col_ind, val_in, strip_ptr, col_word, val_out, workspace, stream);
-        case 4: return from_csr_hb<4, ET>(cv, flags, row_ptr, col_ind, val_in, strip_ptr, col_word, val_out, workspace, stream);
-        case 8: return from_csr_hb<8, ET>(cv, flags, row_ptr, col_ind, val_in, strip_ptr, col_word, val_out, workspace, stream);
-        case 16: return from_csr_hb<16, ET>(cv, flags, row_ptr, col_ind, val_in, strip_ptr, col_word, val_out, workspace, stream);
-        default: return from_csr_hb<32, ET>(cv, flags, row_ptr, col_ind, val_in, strip_ptr, col_word, val_out, workspace, stream);
+        case 1: return from_csr_hb<1, ET>(cv, row_ptr, col_ind, val_in, strip_ptr, col_word, val_out, workspace, stream);
+        case 2: return from_csr_hb<2, ET>(cv, row_ptr, col_ind, val_in, strip_ptr, col_word, val_out, workspace, stream);
+        case 4: return from_csr_hb<4, ET>(cv, row_ptr, col_ind, val_in, strip_ptr, col_word, val_out, workspace, stream);
+        case 8: return from_csr_hb<8, ET>(cv, row_ptr, col_ind, val_in, strip_ptr, col_word, val_out, workspace, stream);
+        case 16: return from_csr_hb<16, ET>(cv, row_ptr, col_ind, val_in, strip_ptr, col_word, val_out, workspace, stream);
+        default: return from_csr_hb<32, ET>(cv, row_ptr, col_ind, val_in, strip_ptr, col_word, val_out, workspace, stream);
     }
 }
 
