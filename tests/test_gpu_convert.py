@@ -212,3 +212,38 @@ def test_validate_csr(C):
     rpc = rp.clone()
     rpc[-1] += 1
     assert C.validate_csr(rpc, ci, A.cols) & 1
+
+
+def _run_totals_matrix(totals, run_rows, cols, spread, seed):
+    """Rows grouped in runs of run_rows rows; run i holds totals[i] entries,
+    all in its first row (spread=False) or dealt round-robin over its rows."""
+    rng = np.random.default_rng(seed)
+    k = np.zeros(len(totals) * run_rows, np.int64)
+    for i, t in enumerate(totals):
+        if spread:
+            k[i * run_rows:(i + 1) * run_rows] = t // run_rows
+            k[i * run_rows:i * run_rows + t % run_rows] += 1
+        else:
+            k[i * run_rows] = t
+    cl = [np.sort(rng.choice(cols, size=int(kk), replace=False)) for kk in k]
+    col = np.concatenate(cl) if cl else np.zeros(0)
+    rp = np.zeros(k.size + 1, np.int64)
+    np.cumsum(k, out=rp[1:])
+    return synth.Csr(k.size, cols, rp.astype(np.int32), col.astype(np.int32), rng.standard_normal(col.size))
+
+
+@pytest.mark.parametrize("spread", [False, True])
+@pytest.mark.parametrize("height", [2, 3, 16, 32])
+def test_run_boundaries(C, height, spread):
+    """Runs of whole strips of up to 32 rows with 0, 1, 63, 64, 767, 768, 769
+    and 1500 entries: the conversions' register and streaming paths and their
+    cut-over, empty runs between full ones, and a ragged last run."""
+    run_rows = (32 // height) * height
+    A = _run_totals_matrix([0, 767, 768, 769, 0, 0, 1, 63, 64, 1500, 768, 5], run_rows, 4000, spread, seed=height)
+    A = synth.Csr(A.rows - 3, A.cols, A.row_ptr[:-3].copy(), A.col_ind[:A.row_ptr[-4]].copy(),
+                  A.val[:A.row_ptr[-4]].copy())
+    for sort in (False, True):
+        M, hv = check_from_csr(C, A, height, sort)
+        rp2, ci2, v2 = check_round_trip(C, A, M, hv)
+        assert np.array_equal(rp2.cpu().numpy(), A.row_ptr) and np.array_equal(ci2.cpu().numpy(), A.col_ind)
+        assert np.array_equal(G.val_bits(v2), A.val.view(np.uint64))
