@@ -569,7 +569,7 @@ def main():
         t1 = time.perf_counter()
         cpu_step()
         first = time.perf_counter() - t1
-        reps = max(1, min(8, int(15.0 / max(first, 1e-3))))
+        reps = max(1, min(32, int(10.0 / max(first, 1e-3))))  # about 10 s of CPU work
         t1 = time.perf_counter()
         for _ in range(reps):
             cpu_step()
