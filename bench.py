@@ -141,19 +141,31 @@ def selector_report(rp, ci, v64, cols):
     del run
     # Fresh matrices (generator seed 1; the timing set used seed 0).
     dev = torch.device("cuda:0")
-    live_t, live_c = [], []
+    # The exhaustive best is picked on one set of timings; the learned choice,
+    # that best and the fixed default are then timed again, and the regret is
+    # taken from the second set (the minimum of 24 noisy times is biased low,
+    # which would otherwise count as regret).
+    live_t, live_c, again = [], [], []
     for i in range(100):
         fam, mrp, mci, mval, mcols = S.sample_matrix(i, 1, dev, max_nnz=20_000_000)
         f = S.features(mrp, mci, mcols)
         live_c.append(int(model.predict(f.reshape(1, -1)).argmin().item()))
         r = S.ClassRunner(mrp, mci, mval, mcols)
         live_t.append(r.time_classes(reps=5))
+        pick = (live_c[-1], int(np.nanargmin(live_t[-1])), S.DEFAULT_CLASS)
+        t2 = r.time_classes(classes=sorted(set(pick)), reps=9)
+        again.append([t2[c] for c in pick])
         del r, mrp, mci, mval
     live_t = np.array(live_t)
     live_c = np.array(live_c)
-    live = {"matrices": 100, "regret": round(S.regret(live_t, live_c), 4),
-            "tune_ratio_geomean": round(1.0 / (1.0 + S.regret(live_t, live_c)), 4),
-            "regret_default_h8_group": round(S.regret(live_t, np.full(100, S.DEFAULT_CLASS)), 4)}
+    again = np.array(again)
+    gm = lambda a, b: float(np.exp(np.mean(np.log(a / b))) - 1.0)
+    live = {"matrices": 100, "regret": round(gm(again[:, 0], again[:, 1]), 4),
+            "tune_ratio_geomean": round(1.0 / (1.0 + gm(again[:, 0], again[:, 1])), 4),
+            "regret_default_h8_group": round(gm(again[:, 2], again[:, 1]), 4),
+            "regret_same_sample": round(S.regret(live_t, live_c), 4),
+            "protocol": "best class picked on 24 timings (median of 5); chosen, best and default re-timed "
+                        "(median of 9) and compared on the second timings"}
     log(f"selector: this workload {here['predicted']} vs best {here['exhaustive_best']} ratio {here['tune_ratio']}; "
         f"fresh regret {live['regret']}; held-out regret {held['regret']}")
     return {"classes": "6 heights x (wave, wave_nt, group, colblock4)", "this_workload": here, "fresh": live,
