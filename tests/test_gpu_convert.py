@@ -189,7 +189,7 @@ def test_c2_full_size(C, c2, height):
     assert np.array_equal(G.val_bits(v2), c2.val.view(np.uint64))
 
 
-@pytest.mark.parametrize("height,sort", [(8, True), (8, False), (32, True)])
+@pytest.mark.parametrize("height,sort", [(2, True), (8, True), (8, False), (16, False), (32, True)])
 def test_c3_full_size(C, c3, height, sort):
     """n = 2e6, Zipf(2) rows up to 10000 entries: long strips in sorted mode."""
     M, hv = check_from_csr(C, c3, height, sort)
