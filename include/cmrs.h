@@ -41,7 +41,8 @@ extern "C" {
 typedef enum {
     CMRS_OK = 0,
     CMRS_ERR_INVALID_VALUE = 1,   /* bad size, height, pointer, dtype or flag   */
-    CMRS_ERR_INDEX_OVERFLOW = 2,  /* cols does not fit the packed column field  */
+    CMRS_ERR_INDEX_OVERFLOW = 2,  /* cols does not fit the packed column field,
+                                     or rows / nnz above CMRS_MAX_INDEX         */
     CMRS_ERR_NOT_SUPPORTED = 3,   /* valid request that this build cannot serve */
     CMRS_ERR_DEVICE = 4,          /* HIP error while enqueueing                 */
     CMRS_ERR_WORKSPACE = 5        /* workspace pointer NULL or too small        */
@@ -61,6 +62,12 @@ typedef enum {
 
 /* Largest supported strip height. */
 #define CMRS_MAX_HEIGHT 32
+
+/* Largest row count and entry count (nnz, padded_nnz) any call accepts,
+ * 2^31 - 2^16: the kernels index rows and entries with 32-bit integers and
+ * step up to 2^16 past the last one inside their loops.  Larger sizes return
+ * CMRS_ERR_INDEX_OVERFLOW before anything is enqueued. */
+#define CMRS_MAX_INDEX 2147418112
 
 /* SpMV kernel variants (cmrs_spmv `variant`). */
 #define CMRS_SPMV_AUTO 0   /* library's choice for (height, dtype)                  */
@@ -323,8 +330,8 @@ cmrs_status_t cmrs_spmm_batched(const cmrs_spmm_plan_t *plan, hipStream_t stream
  * cmrs_padded_plan: counts the chunks of every strip and writes
  *   strip_ptr_out[strips+1] (entry offsets, multiples of 64) and
  *   *padded_nnz_out (host); synchronises `stream` to return the size.
- *   CMRS_ERR_INDEX_OVERFLOW when the padded size exceeds INT32_MAX (the
- *   size is still returned).  Workspace: cmrs_padded_plan_workspace() bytes,
+ *   CMRS_ERR_INDEX_OVERFLOW when the padded size exceeds CMRS_MAX_INDEX
+ *   (the size is still returned).  Workspace: cmrs_padded_plan_workspace() bytes,
  *   8-byte aligned.
  * cmrs_padded_from_csr: fills col_word_out / val_out (padded_nnz entries)
  *   for canonical or any CSR; entries keep their CSR order within a row.

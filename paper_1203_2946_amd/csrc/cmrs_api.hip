@@ -42,6 +42,9 @@ bool cols_fit(int32_t cols, int32_t bits) {
     return static_cast<uint64_t>(cols) <= (static_cast<uint64_t>(1) << (32 - bits));
 }
 
+// Sizes the 32-bit row and entry indexing of the kernels can serve.
+bool size_fits(int64_t n) { return n <= CMRS_MAX_INDEX; }
+
 bool ranges_overlap(const void* a, size_t an, const void* b, size_t bn) {
     if (!a || !b || an == 0 || bn == 0) return false;
     const char* pa = static_cast<const char*>(a);
@@ -55,6 +58,8 @@ cmrs_status_t check_mat(const cmrs_mat_t* A) {
         return fail(CMRS_ERR_INVALID_VALUE, "negative size (rows=%d cols=%d nnz=%d)", A->rows, A->cols, A->nnz);
     if (A->height < 1 || A->height > CMRS_MAX_HEIGHT)
         return fail(CMRS_ERR_INVALID_VALUE, "height %d outside [1, %d]", A->height, CMRS_MAX_HEIGHT);
+    if (!size_fits(A->rows) || !size_fits(A->nnz))
+        return fail(CMRS_ERR_INDEX_OVERFLOW, "rows=%d or nnz=%d above %d", A->rows, A->nnz, CMRS_MAX_INDEX);
     if (A->bits != cmrs_bits_for_height(A->height))
         return fail(CMRS_ERR_INVALID_VALUE, "bits %d != cmrs_bits_for_height(%d) = %d", A->bits, A->height,
                     cmrs_bits_for_height(A->height));
@@ -100,6 +105,8 @@ cmrs_status_t cmrs_from_csr(int32_t rows, int32_t cols, int32_t nnz, const int32
         return fail(CMRS_ERR_INVALID_VALUE, "height %d outside [1, %d]", height, CMRS_MAX_HEIGHT);
     if (flags & ~CMRS_SORT) return fail(CMRS_ERR_INVALID_VALUE, "unknown flags 0x%x", flags);
     if (!valid_dtype(dtype)) return fail(CMRS_ERR_INVALID_VALUE, "unknown dtype %d", (int)dtype);
+    if (!size_fits(rows) || !size_fits(nnz))
+        return fail(CMRS_ERR_INDEX_OVERFLOW, "rows=%d or nnz=%d above %d", rows, nnz, CMRS_MAX_INDEX);
     const int32_t bits = cmrs_bits_for_height(height);
     if (!cols_fit(cols, bits))
         return fail(CMRS_ERR_INDEX_OVERFLOW, "cols=%d does not fit %d column bits", cols, 32 - bits);
@@ -402,6 +409,8 @@ cmrs_status_t cmrs_padded_plan(int32_t rows, int32_t nnz, const int32_t* row_ptr
     if (rows < 0 || nnz < 0) return fail(CMRS_ERR_INVALID_VALUE, "negative size");
     if (height < 1 || height > CMRS_MAX_HEIGHT)
         return fail(CMRS_ERR_INVALID_VALUE, "height %d outside [1, %d]", height, CMRS_MAX_HEIGHT);
+    if (!size_fits(rows) || !size_fits(nnz))
+        return fail(CMRS_ERR_INDEX_OVERFLOW, "rows=%d or nnz=%d above %d", rows, nnz, CMRS_MAX_INDEX);
     if (!row_ptr || !strip_ptr_out || !padded_nnz_out) return fail(CMRS_ERR_INVALID_VALUE, "NULL pointer");
     const size_t need = cmrs_padded_plan_workspace(rows, height);
     if (!workspace || workspace_bytes < need)
@@ -418,8 +427,9 @@ cmrs_status_t cmrs_padded_plan(int32_t rows, int32_t nnz, const int32_t* row_ptr
     if (st != CMRS_OK) return st;
     const long long padded = chunks * 64;
     *padded_nnz_out = padded;
-    if (padded > INT32_MAX)
-        return fail(CMRS_ERR_INDEX_OVERFLOW, "padded matrix would hold %lld entries (int32 offsets)", padded);
+    if (!size_fits(padded))
+        return fail(CMRS_ERR_INDEX_OVERFLOW, "padded matrix would hold %lld entries, above %d", padded,
+                    CMRS_MAX_INDEX);
     return from_hip(cmrs::launch_padded_strip_ptr(strips, workspace, strip_ptr_out, stream), "cmrs_padded_plan");
 }
 
@@ -432,6 +442,8 @@ cmrs_status_t cmrs_padded_from_csr(int32_t rows, int32_t cols, int32_t nnz, cons
     if (height < 1 || height > CMRS_MAX_HEIGHT)
         return fail(CMRS_ERR_INVALID_VALUE, "height %d outside [1, %d]", height, CMRS_MAX_HEIGHT);
     if (!valid_dtype(dtype)) return fail(CMRS_ERR_INVALID_VALUE, "unknown dtype %d", (int)dtype);
+    if (!size_fits(rows) || !size_fits(padded_nnz))
+        return fail(CMRS_ERR_INDEX_OVERFLOW, "rows=%d or padded_nnz=%d above %d", rows, padded_nnz, CMRS_MAX_INDEX);
     if (padded_nnz < nnz || padded_nnz % 64) return fail(CMRS_ERR_INVALID_VALUE, "padded_nnz %d is not a plan's size", padded_nnz);
     const int32_t bits = cmrs_padded_bits(height);
     if (!cols_fit(cols, bits)) return fail(CMRS_ERR_INDEX_OVERFLOW, "cols=%d does not fit %d column bits", cols, 32 - bits);
@@ -471,6 +483,8 @@ cmrs_status_t cmrs_validate_csr(int32_t rows, int32_t cols, int32_t nnz, const i
                                 const int32_t* col_ind, int32_t* flag_out, hipStream_t stream) {
     g_last_error[0] = 0;
     if (rows < 0 || cols < 0 || nnz < 0) return fail(CMRS_ERR_INVALID_VALUE, "negative size");
+    if (!size_fits(rows) || !size_fits(nnz))
+        return fail(CMRS_ERR_INDEX_OVERFLOW, "rows=%d or nnz=%d above %d", rows, nnz, CMRS_MAX_INDEX);
     if (!row_ptr || !flag_out || (nnz > 0 && !col_ind)) return fail(CMRS_ERR_INVALID_VALUE, "NULL pointer");
     return from_hip(cmrs::launch_validate_csr(rows, cols, nnz, row_ptr, col_ind, flag_out, stream),
                     "cmrs_validate_csr");
@@ -501,6 +515,8 @@ cmrs_status_t cmrs_features(int32_t rows, int32_t cols, int32_t nnz, const int32
                             float* feat_out, void* workspace, size_t workspace_bytes, hipStream_t stream) {
     g_last_error[0] = 0;
     if (rows < 0 || cols < 0 || nnz < 0) return fail(CMRS_ERR_INVALID_VALUE, "negative size");
+    if (!size_fits(rows) || !size_fits(nnz))
+        return fail(CMRS_ERR_INDEX_OVERFLOW, "rows=%d or nnz=%d above %d", rows, nnz, CMRS_MAX_INDEX);
     if (!row_ptr || !feat_out || (nnz > 0 && !col_ind)) return fail(CMRS_ERR_INVALID_VALUE, "NULL pointer");
     if (!workspace || workspace_bytes < CMRS_SEL_FEATURE_WS)
         return fail(CMRS_ERR_WORKSPACE, "workspace of %d bytes needed", CMRS_SEL_FEATURE_WS);

@@ -203,3 +203,17 @@ def test_spmm_batched_rejects_corrupt_plan(C):
     p.max_slots, p.lds_bytes = 4, 1024
     assert C.lib.cmrs_spmm_batched(ctypes.byref(p), None) == 1          # LDS below 4 waves x 4 slots x 64 x 8 B
     assert C.lib.cmrs_spmm_batched(None, None) == 1
+
+
+def test_sizes_above_max_index_rejected(C):
+    """rows or nnz above CMRS_MAX_INDEX (2^31 - 2^16) return INDEX_OVERFLOW (2)
+    from the host checks, before anything is enqueued."""
+    big = 2**31 - 2**16 + 1
+    assert _from_csr(C, nnz=big) == 2
+    assert _from_csr(C, rows=big) == 2
+    d = _mat(C, nnz=big)
+    assert C.lib.cmrs_to_csr(ctypes.byref(d), FAKE + 4096, FAKE + 8192, FAKE + 16384, None, 0, None) == 2
+    assert C.lib.cmrs_spmv(ctypes.byref(d), FAKE + 4096, FAKE + 8192, 0, 0, None) == 2
+    d = _mat(C, rows=big)
+    assert C.lib.cmrs_spmv(ctypes.byref(d), FAKE + 4096, FAKE + 8192, 0, 0, None) == 2
+    assert C.lib.cmrs_validate_csr(big, 4, 4, FAKE, FAKE, FAKE, None) == 2
