@@ -455,6 +455,33 @@ __device__ inline RunRound run_round(int myp, int b, int e1, uint32_t w, uint32_
     return rr;
 }
 
+// Waves per workgroup of the CMRS -> CSR kernel, and the run length above
+// which the workgroup's waves share a run.  (2 and 8 waves were measured
+// slower on both the benchmark and the skewed-row matrices.)
+constexpr int kToCsrWaves = 4;
+constexpr int kToCsrThreads = kToCsrWaves * kWave;
+constexpr int kLongRun = 2048;
+
+// One run of the CMRS -> CSR kernel: strips [S, S + nsw), rows [r0, r0 +
+// nrow), entries [e0, e1); lane t <= nsw holds StripPtr[S + t] in myp.
+struct ToCsrRun {
+    int S, nsw, r0, nrow, e0, e1, myp;
+};
+
+__device__ inline ToCsrRun to_csr_run(int run, int ns, int strips, int rows, int height,
+                                      const int* __restrict__ strip_ptr, int lane) {
+    ToCsrRun R;
+    R.S = run * ns;
+    R.nsw = R.S < strips ? min(ns, strips - R.S) : 0;
+    R.myp = (R.nsw > 0 && lane <= R.nsw) ? strip_ptr[R.S + lane] : INT_MAX;
+    const int p0 = __shfl(R.myp, 0), p1 = __shfl(R.myp, R.nsw);
+    R.e0 = R.nsw > 0 ? uniform(p0) : 0;
+    R.e1 = R.nsw > 0 ? uniform(p1) : 0;
+    R.r0 = R.S * height;
+    R.nrow = R.nsw > 0 ? min(R.nsw * height, rows - R.r0) : 0;
+    return R;
+}
+
 // CMRS -> CSR with one wave per run of `ns` whole strips (ns*height <=
 // kRunRows consecutive rows, lane k owning row k of the run).  The run's
 // entries are contiguous, so the wave streams them 64 at a time with
@@ -465,108 +492,163 @@ __device__ inline RunRound run_round(int myp, int b, int e1, uint32_t w, uint32_
 // round: lanes below it with the same key).  The scatter keeps strip order
 // inside every row, the stable order of the inverse conversion.  A run of at
 // most FIT entries is loaded once and both passes work on the registers;
-// longer runs are read twice.
+// longer runs are read twice.  A run of more than kLongRun entries is shared
+// by the workgroup's waves after they have finished their own runs: each wave
+// counts a contiguous slice, the per-row counts of earlier slices (LDS) start
+// its ranks, and each wave scatters its slice.  Every wave reads the lengths
+// of the workgroup's runs and so takes the same barrier-or-not decision; a
+// workgroup without a long run has no barrier.
 template <typename ET>
-__global__ __launch_bounds__(kConvThreads) void to_csr_rows_kernel(
+__global__ __launch_bounds__(kToCsrThreads) __attribute__((amdgpu_waves_per_eu(8))) void to_csr_rows_kernel(
     int rows, int strips, int height, int bits, int ns, const int* __restrict__ strip_ptr,
     const uint32_t* __restrict__ word, const ET* __restrict__ val, int* __restrict__ row_ptr,
     int* __restrict__ col_ind, ET* __restrict__ val_out) {
     constexpr int UF = 12, U = 8, FIT = UF * kWave;
+    __shared__ int slice_cnt[kToCsrWaves][kRunRows];
     const int lane = lane_id();
     const int wave = uniform(static_cast<int>(threadIdx.x) / kWave);
-    const int S = (xcd_logical_block(blockIdx.x, gridDim.x) * kConvWaves + wave) * ns;
-    if (S >= strips) return;
-    const int nsw = min(ns, strips - S);
-    const int myp = lane <= nsw ? strip_ptr[S + lane] : INT_MAX;
-    const int e0 = uniform(__shfl(myp, 0)), e1 = uniform(__shfl(myp, nsw));
-    const int r0 = S * height;
-    const int nrow = min(nsw * height, rows - r0);
+    const int run0 = xcd_logical_block(blockIdx.x, gridDim.x) * kToCsrWaves;
+    const int nruns = (strips + ns - 1) / ns;
     const uint32_t mask = (1u << bits) - 1u;
     const uint64_t lt = lanemask_lt();
 
-    auto row_starts = [&](int cnt) {
+    // This wave's run, loaded before the lengths below so that both loads are
+    // in flight together.
+    const ToCsrRun Rw = to_csr_run(run0 + wave, ns, strips, rows, height, strip_ptr, lane);
+    // Bit r: run run0 + r holds more than kLongRun entries (lanes r <
+    // kToCsrWaves read the runs' first strip pointers, the next kToCsrWaves
+    // lanes their last).
+    uint64_t longs;
+    {
+        const int run = run0 + (lane & (kToCsrWaves - 1));
+        const int sidx = min(run * ns + (lane >= kToCsrWaves ? ns : 0), strips);
+        const int p = (lane < 2 * kToCsrWaves && run < nruns) ? strip_ptr[sidx] : 0;
+        const int pend = __shfl(p, (lane & (kToCsrWaves - 1)) + kToCsrWaves);
+        longs = ballot(lane < kToCsrWaves && run < nruns && pend - p > kLongRun);
+    }
+
+    // CSR starts of the run's rows from per-row counts (lane k: row k);
+    // `write` stores them.
+    auto row_starts = [&](const ToCsrRun& R, int cnt, bool write) {
         int incl = cnt;
 #pragma unroll
         for (int off = 1; off < kRunRows; off <<= 1) {
             const int v = __shfl_up(incl, off);
             if (lane >= off) incl += v;
         }
-        const int start = e0 + incl - cnt;
-        if (lane < nrow) row_ptr[r0 + lane] = start;
-        if (S + nsw == strips && lane == 0) row_ptr[rows] = e1;
+        const int start = R.e0 + incl - cnt;
+        if (write && lane < R.nrow) row_ptr[R.r0 + lane] = start;
+        if (write && R.S + R.nsw == strips && lane == 0) row_ptr[rows] = R.e1;
         return start;
     };
     // Scatter of one round; `next` (lane k): CSR position of the next entry of row k.
-    auto scatter = [&](const RunRound& rr, uint32_t w, ET v, int& next) {
+    auto scatter = [&](const ToCsrRun& R, const RunRound& rr, uint32_t w, ET v, int& next) {
         const int src = rr.key >= 0 ? rr.key : 0;
         const int pos = __shfl(next, src) + __popcll(key_match(src, rr.valid, rr.kb) & lt);
         // pos lies in [e0, e1) by construction; the check keeps a corrupt
         // strip from writing outside its run.
-        if (rr.key >= 0 && static_cast<unsigned>(pos - e0) < static_cast<unsigned>(e1 - e0)) {
+        if (rr.key >= 0 && static_cast<unsigned>(pos - R.e0) < static_cast<unsigned>(R.e1 - R.e0)) {
             col_ind[pos] = static_cast<int>(w >> bits);
             val_out[pos] = v;
         }
         next += __popcll(key_match(lane, rr.valid, rr.kb));
     };
-
-    if (e1 - e0 <= FIT) {
-        uint32_t w[UF];
-        ET v[UF];
-#pragma unroll
-        for (int u = 0; u < UF; ++u) {
-            const int j = e0 + u * kWave + lane;
-            w[u] = j < e1 ? word[j] : 0u;
-            v[u] = j < e1 ? val[j] : ET(0);
-        }
+    // Per-row counts (lane k: row k) of the run's entries [lo, hi).
+    auto count_range = [&](const ToCsrRun& R, int lo, int hi) {
         int cnt = 0, tc = 0;
+        for (int b0 = lo; b0 < hi; b0 += U * kWave) {
+            uint32_t w[U];
 #pragma unroll
-        for (int u = 0; u < UF; ++u) {
-            if (e0 + u * kWave >= e1) break;
-            const RunRound rr = run_round(myp, e0 + u * kWave, e1, w[u], mask, height, nrow, tc);
-            cnt += __popcll(key_match(lane, rr.valid, rr.kb));
-        }
-        int next = row_starts(cnt);
-        tc = 0;
+            for (int u = 0; u < U; ++u) {
+                const int j = b0 + u * kWave + lane;
+                w[u] = j < hi ? word[j] : 0u;
+            }
 #pragma unroll
-        for (int u = 0; u < UF; ++u) {
-            if (e0 + u * kWave >= e1) break;
-            const RunRound rr = run_round(myp, e0 + u * kWave, e1, w[u], mask, height, nrow, tc);
-            scatter(rr, w[u], v[u], next);
+            for (int u = 0; u < U; ++u) {
+                if (b0 + u * kWave >= hi) break;
+                const RunRound rr = run_round(R.myp, b0 + u * kWave, hi, w[u], mask, height, R.nrow, tc);
+                cnt += __popcll(key_match(lane, rr.valid, rr.kb));
+            }
         }
-        return;
+        return cnt;
+    };
+    // Scatter of the run's entries [lo, hi).
+    auto scatter_range = [&](const ToCsrRun& R, int lo, int hi, int& next) {
+        int tc = 0;
+        for (int b0 = lo; b0 < hi; b0 += U * kWave) {
+            uint32_t w[U];
+            ET v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = b0 + u * kWave + lane;
+                w[u] = j < hi ? word[j] : 0u;
+                v[u] = j < hi ? val[j] : ET(0);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (b0 + u * kWave >= hi) break;
+                const RunRound rr = run_round(R.myp, b0 + u * kWave, hi, w[u], mask, height, R.nrow, tc);
+                scatter(R, rr, w[u], v[u], next);
+            }
+        }
+    };
+
+    // This wave's own run, unless it is long.
+    if (run0 + wave < nruns && !((longs >> wave) & 1)) {
+        const ToCsrRun& R = Rw;
+        if (R.e1 - R.e0 <= FIT) {
+            uint32_t w[UF];
+            ET v[UF];
+#pragma unroll
+            for (int u = 0; u < UF; ++u) {
+                const int j = R.e0 + u * kWave + lane;
+                w[u] = j < R.e1 ? word[j] : 0u;
+                v[u] = j < R.e1 ? val[j] : ET(0);
+            }
+            int cnt = 0, tc = 0;
+#pragma unroll
+            for (int u = 0; u < UF; ++u) {
+                if (R.e0 + u * kWave >= R.e1) break;
+                const RunRound rr = run_round(R.myp, R.e0 + u * kWave, R.e1, w[u], mask, height, R.nrow, tc);
+                cnt += __popcll(key_match(lane, rr.valid, rr.kb));
+            }
+            int next = row_starts(R, cnt, true);
+            tc = 0;
+#pragma unroll
+            for (int u = 0; u < UF; ++u) {
+                if (R.e0 + u * kWave >= R.e1) break;
+                const RunRound rr = run_round(R.myp, R.e0 + u * kWave, R.e1, w[u], mask, height, R.nrow, tc);
+                scatter(R, rr, w[u], v[u], next);
+            }
+        } else {
+            int next = row_starts(R, count_range(R, R.e0, R.e1), true);
+            scatter_range(R, R.e0, R.e1, next);
+        }
     }
 
-    int cnt = 0, tc = 0;
-    for (int b0 = e0; b0 < e1; b0 += U * kWave) {
-        uint32_t w[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int j = b0 + u * kWave + lane;
-            w[u] = j < e1 ? word[j] : 0u;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (b0 + u * kWave >= e1) break;
-            const RunRound rr = run_round(myp, b0 + u * kWave, e1, w[u], mask, height, nrow, tc);
-            cnt += __popcll(key_match(lane, rr.valid, rr.kb));
-        }
-    }
-    int next = row_starts(cnt);
-    tc = 0;
-    for (int b0 = e0; b0 < e1; b0 += U * kWave) {
-        uint32_t w[U];
-        ET v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int j = b0 + u * kWave + lane;
-            w[u] = j < e1 ? word[j] : 0u;
-            v[u] = j < e1 ? val[j] : ET(0);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (b0 + u * kWave >= e1) break;
-            const RunRound rr = run_round(myp, b0 + u * kWave, e1, w[u], mask, height, nrow, tc);
-            scatter(rr, w[u], v[u], next);
+    // The workgroup's long runs, shared by all its waves (`longs` is the same
+    // in every wave, so every wave meets the same barriers).
+    if (longs) {
+        for (int r = 0; r < kToCsrWaves; ++r) {
+            if (!((longs >> r) & 1)) continue;
+            const ToCsrRun R = to_csr_run(run0 + r, ns, strips, rows, height, strip_ptr, lane);
+            const int n = R.e1 - R.e0;
+            const int chunk = ((n + kToCsrWaves - 1) / kToCsrWaves + kWave - 1) / kWave * kWave;
+            const int lo = min(R.e0 + wave * chunk, R.e1), hi = min(lo + chunk, R.e1);
+            const int cnt = count_range(R, lo, hi);
+            if (lane < kRunRows) slice_cnt[wave][lane] = cnt;
+            __syncthreads();
+            int tot = 0, before = 0;
+            if (lane < kRunRows) {
+                for (int w2 = 0; w2 < kToCsrWaves; ++w2) {
+                    const int c = slice_cnt[w2][lane];
+                    tot += c;
+                    if (w2 < wave) before += c;
+                }
+            }
+            int next = row_starts(R, tot, wave == 0) + before;
+            scatter_range(R, lo, hi, next);
+            __syncthreads();  // slice_cnt is reused by the next long run
         }
     }
 }
@@ -864,9 +946,9 @@ hipError_t to_csr_typed(const cmrs_mat_t* A, int* row_ptr, int* col_ind, void* v
     const int strips = (A->rows + A->height - 1) / A->height;
     // Whole strips per wave: as many as fit in kRunRows rows (height <= 32).
     const int ns = kRunRows / A->height;
-    const int waves = (strips + ns - 1) / ns;
-    const int blocks = (waves + kConvWaves - 1) / kConvWaves;
-    hipLaunchKernelGGL((to_csr_rows_kernel<ET>), dim3(blocks), dim3(kConvThreads), 0, stream, A->rows, strips,
+    const int runs = (strips + ns - 1) / ns;
+    const int blocks = (runs + kToCsrWaves - 1) / kToCsrWaves;
+    hipLaunchKernelGGL((to_csr_rows_kernel<ET>), dim3(blocks), dim3(kToCsrThreads), 0, stream, A->rows, strips,
                        A->height, A->bits, ns, A->strip_ptr, A->col_word, static_cast<const ET*>(A->val), row_ptr,
                        col_ind, static_cast<ET*>(val_out));
     return hipGetLastError();
