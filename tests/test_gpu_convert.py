@@ -247,3 +247,22 @@ def test_run_boundaries(C, height, spread):
         rp2, ci2, v2 = check_round_trip(C, A, M, hv)
         assert np.array_equal(rp2.cpu().numpy(), A.row_ptr) and np.array_equal(ci2.cpu().numpy(), A.col_ind)
         assert np.array_equal(G.val_bits(v2), A.val.view(np.uint64))
+
+
+@pytest.mark.parametrize("spread", [False, True])
+@pytest.mark.parametrize("height", [2, 5, 32])
+def test_shared_long_runs(C, height, spread):
+    """CMRS -> CSR runs of more than 2048 entries are shared by the waves of a
+    workgroup: runs just below and above that length, several long runs in one
+    workgroup (runs 4..7), a long run between short ones and a long ragged last
+    run, sorted and unsorted."""
+    run_rows = (32 // height) * height
+    totals = [2047, 2048, 2049, 10, 5000, 9001, 3000, 2100, 0, 64, 4097, 1, 6000]
+    A = _run_totals_matrix(totals, run_rows, 20000, spread, seed=40 + height)
+    A = synth.Csr(A.rows - 2, A.cols, A.row_ptr[:-2].copy(), A.col_ind[:A.row_ptr[-3]].copy(),
+                  A.val[:A.row_ptr[-3]].copy())
+    for sort in (False, True):
+        M, hv = check_from_csr(C, A, height, sort)
+        rp2, ci2, v2 = check_round_trip(C, A, M, hv)
+        assert np.array_equal(rp2.cpu().numpy(), A.row_ptr) and np.array_equal(ci2.cpu().numpy(), A.col_ind)
+        assert np.array_equal(G.val_bits(v2), A.val.view(np.uint64))
