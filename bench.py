@@ -563,7 +563,9 @@ def main():
                "stream_read_frac_of_peak": round(stream_bytes / ts / 1e6 / HBM_PEAK_GBS, 4),
                "random_gathers_per_s": round(A.nnz / (tg * 1e-3), 1),
                "random_gather_ms_for_nnz": round(tg, 5),
-               "spmv_eta_plus_vs_stream_ceiling": round(b_spmv / cm / 1e6 / (stream_bytes / ts / 1e6), 4)}
+               "spmv_eta_plus_vs_stream_ceiling": round(b_spmv / cm / 1e6 / (stream_bytes / ts / 1e6), 4),
+               # time of the nnz random gathers alone over the SpMV's time (1.0: the SpMV runs at the gather floor)
+               "gather_floor_over_spmv": round(tg / cm, 4)}
     log(f"ceilings: stream {ceiling['stream_read_gbs']} GB/s, gathers {ceiling['random_gathers_per_s'] / 1e9:.1f} G/s")
 
     # ---------------------------------------------------------------- CPU oracle baseline
