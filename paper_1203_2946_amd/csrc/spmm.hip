@@ -189,7 +189,7 @@ constexpr int kQueueStride = 16;
 constexpr int kQueueDone = kNumXcd * kQueueStride;
 
 template <typename VT, typename XT, typename AT>
-__global__ __launch_bounds__(kSpmmMaxWaves * kWave) void spmm_persistent_kernel(
+__global__ __launch_bounds__(kSpmmMaxWaves * kWave) __attribute__((amdgpu_waves_per_eu(4))) void spmm_persistent_kernel(
     const SpmmMat* __restrict__ mats, const SpmmTile* __restrict__ tiles, int ntiles, unsigned* __restrict__ queue,
     int waves_total, int wave_slots) {
     extern __shared__ __align__(16) unsigned char spmm_lds[];
