@@ -71,3 +71,14 @@ def cmrs_by_definition(rows, height, coo_in_crs_order, sorted_=False):
             vals.append(v)
         strip_ptr.append(len(cols))
     return strip_ptr, cols, ris, vals
+
+
+def exact_absmv(rows, coo, x):
+    """(|A||x|)_i = sum over the entries of row i of |a_ij| |x_j|, exact
+    (rationals).  The scale of the componentwise error bound; repeated
+    (row, col) entries each contribute their own term, as each is a separate
+    product in y = A x."""
+    out = [Fraction(0)] * rows
+    for i, j, v in coo:
+        out[i] += abs(Fraction(float(v))) * abs(Fraction(float(x[j])))
+    return out

@@ -270,6 +270,67 @@ def test_negative_zero_products_give_positive_zero():
     assert y[0] == 0.0 and not np.signbit(y[0])
 
 
+# ------------------------------------------------------------ |A||x| pins
+def test_absmv_of_M_with_signed_x(paper):
+    """|M||x| for the printed M and a signed x equals M|x| (all entries of M are
+    positive), here [9, 26, 45, 98, 50]; the plain product with the same signed
+    x differs, so an absolute value dropped on either factor fails."""
+    rp, ci, v = _crs_M(paper)
+    xs = np.array([1.0, -2.0, 3.0, -4.0, 5.0])
+    a = oracle.csr_absmv(rp, ci, v, xs)
+    assert a.tolist() == [9.0, 26.0, 45.0, 98.0, 50.0]
+    assert oracle.csr_absmv(rp, ci, -v, xs).tolist() == a.tolist()
+    assert not np.array_equal(oracle.csr_spmv(rp, ci, v, xs), a)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_absmv_integer_exact(seed):
+    """Small signed integers: every partial sum of |a||x| is exact, so the
+    oracle must equal the rational definition bit for bit (duplicates, empty
+    rows and explicit zeros included)."""
+    A = synth.random_csr(40, 30, max_row=14, seed=300 + seed, int_values=True, duplicates=True,
+                         explicit_zeros=seed % 2 == 0)
+    x = np.random.default_rng(seed).integers(-6, 7, A.cols).astype(np.float64)
+    a = oracle.csr_absmv(A.row_ptr, A.col_ind, A.val, x)
+    ex = brute.exact_absmv(A.rows, brute.coo_from_csr(A.row_ptr, A.col_ind, A.val), x.tolist())
+    assert [Fraction(float(t)) for t in a] == ex
+    k = np.diff(A.row_ptr)
+    assert np.all(a[k == 0] == 0.0)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_absmv_within_gamma_k_of_exact(seed):
+    """Random real data: all terms are non-negative, so recursive summation of
+    k_i rounded products is within gamma_{k_i} of the exact sum, relatively.
+    A row counted twice, a wrong range end or a missing term is off by O(1)."""
+    A = synth.random_csr(30, 50, max_row=20, seed=400 + seed, duplicates=seed % 2 == 1, explicit_zeros=True)
+    x = np.random.default_rng(seed).standard_normal(A.cols)
+    a = oracle.csr_absmv(A.row_ptr, A.col_ind, A.val, x)
+    ex = brute.exact_absmv(A.rows, brute.coo_from_csr(A.row_ptr, A.col_ind, A.val), x.tolist())
+    k = np.diff(A.row_ptr)
+    u = Fraction(1, 2**53)
+    for i in range(A.rows):
+        ki = int(k[i])
+        gamma = ki * u / (1 - ki * u) if ki else Fraction(0)
+        assert abs(Fraction(float(a[i])) - ex[i]) <= gamma * ex[i]
+        assert a[i] >= 0.0
+
+
+def test_absmv_dominates_product():
+    """|y_i| <= (|A||x|)_i for the exact product, with equality for rows whose
+    products share one sign (here: non-negative data)."""
+    A = synth.random_csr(50, 40, max_row=12, seed=9)
+    x = synth.normal_vector(A.cols, seed=10)
+    coo = brute.coo_from_csr(A.row_ptr, A.col_ind, A.val)
+    ex_y = brute.exact_matvec(A.rows, coo, x.tolist())
+    ex_a = brute.exact_absmv(A.rows, coo, x.tolist())
+    assert all(abs(yi) <= ai for yi, ai in zip(ex_y, ex_a))
+    pos = np.abs(A.val)
+    xp = np.abs(x)
+    assert np.array_equal(oracle.csr_absmv(A.row_ptr, A.col_ind, A.val, x),
+                          oracle.csr_spmv(A.row_ptr, A.col_ind, pos, xp))
+
+
 # ------------------------------------------------------------ precision helpers
 def test_bf16_rounding_rne():
     # 1 + 2^-8 is halfway between bf16 neighbours 1 and 1 + 2^-7: ties to even -> 1
