@@ -13,9 +13,16 @@ Before the timed steps every strip height 1..32 and SpMV schedule is measured
 with the paper's protocol (11 calls, the longest dropped, mean and std of the
 rest; Sec. 6.3), cold (L2 and MALL flushed by a 1 GiB write before each call)
 and warm, for fp64 and fp32.  Unless --height / --schedule are given, the timed
-steps use the (height, schedule) with the shortest fp64 step.
+steps of each precision use the (height, schedule) with the fastest cold SpMV.
 
-Prints one JSON line on stdout; progress goes to stderr.
+The headline `value` is the fp64 SpMV's beta+ rate (Eq. 6.1: bytes with x read
+once, over the SpMV's time, from HIP events inside the K timed fp64 steps);
+the same K steps are then run in fp32.  `ms_per_step` is the fp64 step.
+
+Prints one short JSON line on stdout (headline, roofline, CPU baseline and a
+one-line summary of every report); the full sweep and report tables go to the
+detail file (--detail, default gpurun_out/bench_detail.json).  Progress goes
+to stderr.
 """
 from __future__ import annotations
 
@@ -64,6 +71,7 @@ def parse():
                    help="run only that report (for profiling) and print it as one JSON line")
     p.add_argument("--batched-fixed", default=None,
                    help="skip the batched autotuner: dtype=height:tile_nnz:group:blocks_per_cu[,dtype=...]")
+    p.add_argument("--detail", default=None, help="path of the detail JSON (default gpurun_out/bench_detail.json)")
     p.add_argument("--copy-calib", action="store_true",
                    help="only run three plain 1 GiB device-to-device copies (calibrates HBM byte counters)")
     return p.parse_args()
@@ -230,6 +238,26 @@ def batched_report(fixed=None):
     return out
 
 
+def _cold_ms(fn, reps=11):
+    """Paper protocol with L2 and MALL flushed (1 GiB write) before each call:
+    mean of the 10 shortest of 11."""
+    import torch
+    buf = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    fn()
+    pairs = []
+    for _ in range(reps):
+        buf.fill_(1)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        pairs.append((a, b))
+    torch.cuda.synchronize()
+    t = sorted(a.elapsed_time(b) for a, b in pairs)[:-1]
+    del buf
+    return float(np.mean(t))
+
+
 def precision_report():
     """The skewed-row workload in fp64, fp32 and bf16-value/fp32-accumulate:
     SpMV throughput and componentwise error against the fp64 oracle."""
@@ -253,8 +281,12 @@ def precision_report():
             x = torch.from_numpy(x64).to(dev)
             sv, sx, u, rep = 8, 8, 2.0 ** -53, 0.0
         else:
-            v = torch.from_numpy(A.val).to(dev).to(torch.float32 if dt == "f32" else torch.bfloat16)
-            x = torch.from_numpy(x64).to(dev).float()
+            # Stored values rounded once from fp64 on the host (bf16 directly, not through fp32).
+            if dt == "f32":
+                v = torch.from_numpy(synth.round_to_f32(A.val)).to(dev)
+            else:
+                v = torch.from_numpy(synth.round_to_bf16_bits(A.val).view(np.int16).copy()).view(torch.bfloat16).to(dev)
+            x = torch.from_numpy(synth.round_to_f32(x64)).to(dev)
             sv, sx, u, rep = (4 if dt == "f32" else 2), 4, 2.0 ** -24, (0.0 if dt == "f32" else 2.0 ** -8)
         best = None
         for h in (4, 8, 16):
@@ -265,18 +297,22 @@ def precision_report():
                 best = (tm, h, y, M.strips)
             del M
         tm, h, y, strips = best
+        M = cmrs.from_csr(rp, ci, v, A.cols, h, sort=True)
+        tc = _cold_ms(lambda: cmrs.spmv(M, x))
+        del M
         bp = model.beta_plus(A.nnz, A.rows, A.cols, strips, sv, sx, sx)
         err = np.abs(y - yref)
         # Bound of the path: fp64 4 k u |A||x|; fp32 / bf16 values with fp32 x: rounding of the stored value
         # (bf16: 2^-8) and of x (2^-24) plus fp32 accumulation.
         bound = 4 * k * u * absmv if dt == "f64" else 2.0 * (rep + (k + 2) * u) * absmv
         nz = absmv > 0
-        out[dt] = {"height": h, "spmv_warm_ms": round(tm, 5), "gbs_plus": round(bp / tm / 1e6, 1),
-                   "frac_of_hbm_peak": round(bp / tm / 1e6 / HBM_PEAK_GBS, 4),
+        out[dt] = {"height": h, "spmv_warm_ms": round(tm, 5), "spmv_cold_ms": round(tc, 5),
+                   "gbs_plus": round(bp / tc / 1e6, 1), "frac_of_hbm_peak": round(bp / tc / 1e6 / HBM_PEAK_GBS, 4),
+                   "gbs_plus_warm": round(bp / tm / 1e6, 1),
                    "max_err_over_bound": float((err[nz] / bound[nz]).max()) if nz.any() else 0.0,
                    "rows_over_bound": int((err > bound).sum()),
                    "max_componentwise_rel_err": float((err[nz] / absmv[nz]).max()) if nz.any() else 0.0}
-        log(f"precision {dt}: h={h} {tm * 1e3:.1f} us ({bp / tm / 1e6:.0f} GB/s), max err/bound "
+        log(f"precision {dt}: h={h} cold {tc * 1e3:.1f} us ({bp / tc / 1e6:.0f} GB/s), warm {tm * 1e3:.1f} us, max err/bound "
             f"{out[dt]['max_err_over_bound']:.3g}")
     return out
 
@@ -342,6 +378,126 @@ def padded_report(rp, ci, v64, x, cols, nnz, best_plain_ms):
     return out
 
 
+def cpu_baseline_report(A, x64, beta_csr):
+    """The oracle's CSR product on the host cores (a baseline, not the target):
+    ora_csr_spmv serially and ora_csr_spmv_par over every host core with
+    nnz-balanced row ranges, both from the same C source compiled here with
+    -O3 -march=native -ffp-contract=off -fopenmp.  Paper protocol (Sec. 6.3):
+    11 calls, the longest dropped, mean and std of the other 10."""
+    import tempfile
+    import oracle
+    lib = oracle._load(oracle.build_baseline(tempfile.mkdtemp(prefix="cmrs_cpu_")))
+    threads = os.cpu_count() or 1
+
+    def protocol(fn, reps=11):
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        ts = sorted(ts)[:-1]
+        return float(np.mean(ts)), float(np.std(ts))
+
+    y1 = oracle.csr_spmv(A.row_ptr, A.col_ind, A.val, x64, lib=lib)
+    yp, used = oracle.csr_spmv_par(A.row_ptr, A.col_ind, A.val, x64, threads, lib=lib)
+    same = bool(np.array_equal(y1.view(np.uint64), yp.view(np.uint64)))
+    t1, s1 = protocol(lambda: oracle.csr_spmv(A.row_ptr, A.col_ind, A.val, x64, lib=lib))
+    tp, sp = protocol(lambda: oracle.csr_spmv_par(A.row_ptr, A.col_ind, A.val, x64, threads, lib=lib))
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    out = {"value": round(beta_csr / tp / 1e9, 3), "unit": "GB/s", "cores": used, "kind": "oracle",
+           "sample": f"CSR y=Ax, fp64, the full {A.rows}-row workload matrix, 11 calls, longest dropped, mean of 10; "
+                     f"beta+ of the CSR arrays ({beta_csr} B)",
+           "ms": round(tp * 1e3, 3), "ms_std": round(sp * 1e3, 3),
+           "serial": {"value": round(beta_csr / t1 / 1e9, 3), "cores": 1, "ms": round(t1 * 1e3, 3),
+                      "ms_std": round(s1 * 1e3, 3)},
+           "cpu_model": model, "os_cpu_count": os.cpu_count(), "build": "gcc -O3 -march=native -ffp-contract=off -fopenmp",
+           "parallel_equals_serial_bits": same}
+    log(f"cpu oracle: serial {t1 * 1e3:.1f} ms ({out['serial']['value']} GB/s), {used} threads {tp * 1e3:.1f} ms "
+        f"({out['value']} GB/s) on {model}")
+    return out
+
+
+def model_vs_sweep(sweep, mu):
+    """Eq. (5.2): predicted speedup a(h, mu) of strips of height h over h = 1
+    (the vector kernel), for lambda-byte segments and b-byte items, against the
+    measured SpMV speedup t(h=1)/t(h) of the one-wave-per-strip schedule
+    (Algorithm 1 as laid out in the paper) and of the best schedule per h."""
+    from paper_1203_2946_amd import model
+    out = {"mu": round(mu, 3), "rows": []}
+    for dt in ("f64", "f32"):
+        rows = [r for r in sweep if r["dtype"] == dt]
+        if not rows:
+            continue
+        wave = {r["height"]: r["spmv_cold_ms"] for r in rows if r["schedule"] == "wave"}
+        best = {}
+        for r in rows:
+            best[r["height"]] = min(best.get(r["height"], 1e30), r["spmv_cold_ms"])
+        for h in sorted(wave):
+            out["rows"].append({
+                "dtype": dt, "height": h,
+                "a_lambda128_b4": round(model.a_model(h, mu, 128.0, 4.0), 3),
+                "a_lambda64_b4": round(model.a_model(h, mu, 64.0, 4.0), 3),
+                "a_lambda128_bval": round(model.a_model(h, mu, 128.0, float(model.dtype_size(dt))), 3),
+                "measured_wave": round(wave[1] / wave[h], 3) if 1 in wave else None,
+                "measured_best": round(best[1] / best[h], 3) if 1 in best else None})
+    return out
+
+
+def compact_line(res: dict) -> str:
+    """The one stdout JSON line: the headline, the roofline, the CPU baseline
+    and one-line summaries of every report (the full tables go to the detail
+    file).  Raises if it would exceed 4000 characters."""
+    def pick(d, keys):
+        return {k: d[k] for k in keys if d is not None and k in d}
+
+    ex = res.get("extras", {})
+    summ = {}
+    if "selector" in ex:
+        s = ex["selector"]
+        summ["selector"] = {"tune_ratio": s["this_workload"]["tune_ratio"],
+                            "choice": s["this_workload"]["predicted"], "best": s["this_workload"]["exhaustive_best"],
+                            "regret_fresh": s["fresh"]["regret"], "regret_held_out": s["held_out"]["regret"],
+                            "regret_default": s["fresh"]["regret_default_h8_group"]}
+    if "precision" in ex:
+        p = ex["precision"]
+        summ["precision_zipf"] = {dt: pick(p[dt], ("height", "spmv_cold_ms", "gbs_plus", "frac_of_hbm_peak",
+                                                   "max_err_over_bound", "rows_over_bound"))
+                                  for dt in ("f64", "f32", "bf16") if dt in p}
+    if "batched" in ex:
+        b = ex["batched"]
+        summ["batched"] = {dt: pick(b[dt], ("graph_persistent_ms", "separate_launches_ms", "speedup_vs_separate",
+                                            "frac_of_hbm_peak")) for dt in ("f64", "f32") if dt in b}
+    if "structured" in ex:
+        summ["structured"] = {k: {dt: v[dt]["eta_plus"] for dt in ("f64", "f32") if dt in v}
+                              for k, v in ex["structured"].items()}
+    if "padded" in ex:
+        summ["padded"] = {k: pick(v, ("memory_overhead", "speedup_vs_best_plain")) for k, v in ex["padded"].items()}
+    if "model" in ex:
+        summ["model_eq52"] = [[r["dtype"], r["height"], r["a_lambda128_b4"], r["measured_wave"], r["measured_best"]]
+                              for r in ex["model"]["rows"]]
+    line = {k: res[k] for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+                                 "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config",
+                                 "roofline", "cpu_baseline") if k in res}
+    for k in ("spmv", "step", "ceiling"):
+        if k in res:
+            line[k] = res[k]
+    if summ:
+        line["reports"] = summ
+    if "detail_file" in res:
+        line["detail_file"] = res["detail_file"]
+    txt = json.dumps(line, separators=(",", ":"))
+    if len(txt) > 4000:
+        raise ValueError(f"bench line is {len(txt)} characters (limit 4000)")
+    return txt
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -383,8 +539,8 @@ def main():
     rp = torch.from_numpy(A.row_ptr).to(dev)
     ci = torch.from_numpy(A.col_ind).to(dev)
     v64 = torch.from_numpy(A.val).to(dev)
-    v_d = {"f64": v64, "f32": v64.float()}
-    x_d = {"f64": torch.from_numpy(x64).to(dev), "f32": torch.from_numpy(x64).to(dev).float()}
+    v_d = {"f64": v64, "f32": torch.from_numpy(synth.round_to_f32(A.val)).to(dev)}
+    x_d = {"f64": torch.from_numpy(x64).to(dev), "f32": torch.from_numpy(synth.round_to_f32(x64)).to(dev)}
     flush_buf = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
     sizes = {"f64": 8, "f32": 4}
@@ -457,7 +613,7 @@ def main():
             b_to = model.to_csr_bytes(A.nnz, A.rows, self.M.strips, s_v)
             return b_from, b_plan, bp, bm, b_to
 
-    # ---------------------------------------------------------------- sweep
+    # ---------------------------------------------------------------- sweep (paper protocol, cold and warm)
     sweep = []
     if not args.no_sweep:
         for dt in ("f64", "f32"):
@@ -487,136 +643,134 @@ def main():
                         f"eta+ {r['eta_plus_cold']:.3f}) warm {wm * 1e3:7.1f} us | step {r['step_ms'] * 1e3:7.1f} us")
                     del P
 
-    dt = args.dtype
-    cand = [r for r in sweep if r["dtype"] == dt]
-    if args.height and args.schedule:
-        h, sched = args.height, args.schedule
-    elif cand:
+    def choose(dt):
+        """(height, schedule) of the timed steps: the fastest cold SpMV of the
+        sweep unless --height / --schedule fix them."""
+        cand = [r for r in sweep if r["dtype"] == dt]
+        if args.height and args.schedule:
+            return args.height, args.schedule
         pool = [r for r in cand if (not args.height or r["height"] == args.height)
                 and (not args.schedule or r["schedule"] == args.schedule)]
-        best = min(pool, key=lambda r: r["step_ms"])
-        h, sched = best["height"], best["schedule"]
-    else:
-        h, sched = args.height or 8, args.schedule or "group"
-    log(f"timed steps: dtype={dt} height={h} schedule={sched}")
+        if pool:
+            best = min(pool, key=lambda r: r["spmv_cold_ms"])
+            return best["height"], best["schedule"]
+        return args.height or 32, args.schedule or "colblock4"
 
     # ---------------------------------------------------------------- timed steps
-    P = Pipeline(dt, h, sched)
-    names = ["from_csr_sorted", "colblock_plan", "spmv", "to_csr"] if P.nb else ["from_csr_sorted", "spmv", "to_csr"]
-    calls = [P.convert, P.make_plan, P.spmv, P.back] if P.nb else [P.convert, P.spmv, P.back]
+    def timed_steps(dt):
+        h, sched = choose(dt)
+        P = Pipeline(dt, h, sched)
+        names = ["from_csr_sorted", "colblock_plan", "spmv", "to_csr"] if P.nb else ["from_csr_sorted", "spmv", "to_csr"]
+        calls = [P.convert, P.make_plan, P.spmv, P.back] if P.nb else [P.convert, P.spmv, P.back]
 
-    def step(evs=None):
-        for k, fn in enumerate(calls):
+        def step(evs=None):
+            for k, fn in enumerate(calls):
+                if evs is not None:
+                    evs[k].record(stream)
+                fn()
             if evs is not None:
-                evs[k].record(stream)
-            fn()
-        if evs is not None:
-            evs[len(calls)].record(stream)
+                evs[len(calls)].record(stream)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    all_evs = [[ev() for _ in range(len(calls) + 1)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        step(all_evs[i])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    ms_per_step = wall * 1e3 / args.steps
-    seg_ms = np.array([[e[k].elapsed_time(e[k + 1]) for k in range(len(calls))] for e in all_evs]).mean(axis=0)
+        for _ in range(args.warmup):
+            step()
+        all_evs = [[ev() for _ in range(len(calls) + 1)] for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for i in range(args.steps):
+            step(all_evs[i])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        seg = np.array([[e[k].elapsed_time(e[k + 1]) for k in range(len(calls))] for e in all_evs]).mean(axis=0)
+        b_from, b_plan, bp, bm, b_to = P.bytes()
+        algb = {"from_csr_sorted": b_from, "colblock_plan": b_plan, "spmv": bp, "to_csr": b_to}
+        kern = {n: {"ms": round(float(seg[k]), 5), "gbs": round(algb[n] / seg[k] / 1e6, 1)} for k, n in enumerate(names)}
+        t_spmv = float(seg[names.index("spmv")])
+        log(f"{dt} steps h={h} {sched}: {wall * 1e3 / args.steps * 1e3:.1f} us/step ("
+            + ", ".join(f"{n} {seg[k] * 1e3:.1f}" for k, n in enumerate(names)) + " us)")
+        cm, cs = protocol(P.spmv, cold=True)
+        res = {"height": h, "schedule": sched, "ms": round(t_spmv, 5), "gbs_plus": round(bp / t_spmv / 1e6, 1),
+               "eta_plus": round(bp / t_spmv / 1e6 / HBM_PEAK_GBS, 4), "gbs_minus": round(bm / t_spmv / 1e6, 1),
+               "eta_minus": round(bm / t_spmv / 1e6 / HBM_PEAK_GBS, 4),
+               "gflops": round(model.flops(A.nnz, A.rows) / t_spmv / 1e6, 1),
+               "beta_plus_bytes": bp, "cold_ms": round(cm, 5), "cold_std_ms": round(cs, 5),
+               "cold_eta_plus": round(bp / cm / 1e6 / HBM_PEAK_GBS, 4)}
+        step_bytes = sum(algb[n] for n in names)
+        steprec = {"ms": round(wall * 1e3 / args.steps, 5), "gbs": round(step_bytes / (wall / args.steps) / 1e9, 1),
+                   "kernels": kern, "alg_bytes": step_bytes, "calls": " + ".join(names)}
+        return P, res, steprec, wall
 
-    b_from, b_plan, b_spmv, b_spmv_minus, b_to = P.bytes()
-    algb = {"from_csr_sorted": b_from, "colblock_plan": b_plan, "spmv": b_spmv, "to_csr": b_to}
-    b_step = sum(algb[n] for n in names)
-    value = b_step / (ms_per_step * 1e-3) / 1e9
-    kern = {n: {"ms": round(float(seg_ms[k]), 5), "alg_bytes": algb[n],
-                "gbs": round(algb[n] / seg_ms[k] / 1e6, 1)} for k, n in enumerate(names)}
-    dom_name = max(kern, key=lambda k: kern[k]["ms"])
-    dom = kern[dom_name]
-    ach = dom["alg_bytes"] / dom["ms"] / 1e6
-    tag = f"{dom_name}:{dt}:h{h}:{sched}"
+    P64, spmv64, step64, wall64 = timed_steps("f64")
+    ms_per_step = wall64 * 1e3 / args.steps
+    value = spmv64["gbs_plus"]
+    P32, spmv32, step32, _ = timed_steps(args.dtype if args.dtype == "f32" else "f32")
+    tag = f"spmv:f64:h{spmv64['height']}:{spmv64['schedule']}"
     traffic = read_traffic(tag)
-    roofline = {"bound": "hbm", "kernel": dom_name, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic}
-    log(f"step {ms_per_step * 1e3:.1f} us (" + ", ".join(f"{n} {seg_ms[k] * 1e3:.1f}" for k, n in enumerate(names))
-        + f" us) -> {value:.1f} GB/s")
-
-    # SpMV alone at the chosen configuration, paper protocol
-    cm, cs = protocol(P.spmv, cold=True)
-    wm, _ = protocol(P.spmv, cold=False)
-    spmv = {"height": h, "schedule": sched, "dtype": dt, "cold_ms": round(cm, 5), "cold_std_ms": round(cs, 5),
-            "warm_ms": round(wm, 5), "beta_plus_bytes": b_spmv, "beta_minus_bytes": b_spmv_minus,
-            "gbs_plus_cold": round(b_spmv / cm / 1e6, 1), "eta_plus_cold": round(b_spmv / cm / 1e6 / HBM_PEAK_GBS, 4),
-            "gbs_minus_cold": round(b_spmv_minus / cm / 1e6, 1),
-            "eta_minus_cold": round(b_spmv_minus / cm / 1e6 / HBM_PEAK_GBS, 4),
-            "gflops_cold": round(model.flops(A.nnz, A.rows) / cm / 1e6, 1),
-            "gbs_plus_warm": round(b_spmv / wm / 1e6, 1)}
+    roofline = {"bound": "hbm", "kernel": f"SpMV f64 h={spmv64['height']} {spmv64['schedule']}",
+                "achieved": spmv64["gbs_plus"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(spmv64["gbs_plus"] / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "alg_bytes_per_launch": spmv64["beta_plus_bytes"], "launch_ms": spmv64["ms"]}
 
     # Achievable ceilings: read-only pass over the streams (Sec. 6.3) and the random-gather rate into x.
     sink = torch.zeros(1, dtype=torch.float64, device=dev)
-    ts, _ = protocol(lambda: cmrs.calib_stream_read(P.M, h, sink), cold=True)
-    stream_bytes = (4 + sizes[dt]) * A.nnz
+    ts, _ = protocol(lambda: cmrs.calib_stream_read(P64.M, P64.h, sink), cold=True)
+    stream_bytes = 12 * A.nnz
     idx = torch.from_numpy(np.random.default_rng(2).integers(0, A.cols, A.nnz).astype(np.int32)).to(dev)
-    tg, _ = protocol(lambda: cmrs.calib_gather(idx, P.x, sink), cold=True)
+    tg, _ = protocol(lambda: cmrs.calib_gather(idx, P64.x, sink), cold=True)
     ceiling = {"stream_read_gbs": round(stream_bytes / ts / 1e6, 1),
-               "stream_read_frac_of_peak": round(stream_bytes / ts / 1e6 / HBM_PEAK_GBS, 4),
-               "random_gathers_per_s": round(A.nnz / (tg * 1e-3), 1),
-               "random_gather_ms_for_nnz": round(tg, 5),
-               "spmv_eta_plus_vs_stream_ceiling": round(b_spmv / cm / 1e6 / (stream_bytes / ts / 1e6), 4),
+               "gathers_per_s": round(A.nnz / (tg * 1e-3) / 1e9, 2),
                # time of the nnz random gathers alone over the SpMV's time (1.0: the SpMV runs at the gather floor)
-               "gather_floor_over_spmv": round(tg / cm, 4)}
-    log(f"ceilings: stream {ceiling['stream_read_gbs']} GB/s, gathers {ceiling['random_gathers_per_s'] / 1e9:.1f} G/s")
+               "gather_floor_over_spmv": round(tg / spmv64["cold_ms"], 4)}
+    log(f"ceilings: stream {ceiling['stream_read_gbs']} GB/s, gathers {ceiling['gathers_per_s']} G/s")
+    del idx, P32
 
-    # ---------------------------------------------------------------- CPU oracle baseline
     cpu = None
     if not args.no_cpu:
-        import oracle
-        hv = A.val if dt == "f64" else synth.round_to_f32(A.val)
-        xs = x64 if dt == "f64" else synth.round_to_f32(x64).astype(np.float64)
-
-        def cpu_step():
-            sp_, w_, vo_ = oracle.csr_to_cmrs(A.row_ptr, A.col_ind, hv, A.cols, h, sorted_=True)
-            oracle.csr_spmv(A.row_ptr, A.col_ind, hv.astype(np.float64), xs)
-            oracle.cmrs_to_csr(sp_, w_, vo_, A.rows, h)
-
-        t1 = time.perf_counter()
-        cpu_step()
-        first = time.perf_counter() - t1
-        reps = max(1, min(32, int(10.0 / max(first, 1e-3))))  # about 10 s of CPU work
-        t1 = time.perf_counter()
-        for _ in range(reps):
-            cpu_step()
-        tc = (time.perf_counter() - t1) / reps
-        b_cpu = b_from + b_spmv + b_to
-        cpu = {"value": round(b_cpu / tc / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-               "sample": f"the full workload matrix, one step (oracle CSR->CMRS sorted, CSR SpMV, CMRS->CSR; "
-                         f"{b_cpu} algorithmic bytes) timed {reps}x after one untimed pass; {tc:.2f} s per step",
-               "ms_per_step": round(tc * 1e3, 1)}
-        log(f"cpu oracle: {tc:.2f} s/step -> {cpu['value']} GB/s")
+        beta_csr = model.beta_plus(A.nnz, A.rows, A.cols, A.rows, 8, 8, 8)
+        cpu = cpu_baseline_report(A, x64, beta_csr)
 
     extras = {}
+    if sweep:
+        extras["model"] = model_vs_sweep(sweep, A.nnz / A.rows)
     if not args.no_extras:
-        warm_plain = [r["spmv_warm_ms"] for r in sweep if r["dtype"] == "f64"]
-        best_plain = min(warm_plain) if warm_plain else protocol(P.spmv, cold=False)[0]
+        best_plain = min([r["spmv_cold_ms"] for r in sweep if r["dtype"] == "f64"] or [spmv64["cold_ms"]])
+        del P64
+        torch.cuda.empty_cache()
         extras["padded"] = padded_report(rp, ci, v64, x_d["f64"], A.cols, A.nnz, best_plain)
         extras["selector"] = selector_report(rp, ci, v64, A.cols)
         extras["precision"] = precision_report()
         extras["structured"] = structured_report()
         extras["batched"] = batched_report()
 
-    out = {
-        "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+    res = {
+        "metric": METRIC, "value": value, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": dt, "data": "synthetic",
-        "config": {"workload": f"poisson16 n={A.rows} (row lengths max(1,Poisson(16)), distinct uniform columns, "
-                               f"N(0,1) values and x, seed 0)", "rows": A.rows, "nnz": A.nnz, "height": h,
-                   "schedule": sched, "sorted": True,
-                   "step": " + ".join(names), "alg_bytes_per_step": b_step},
-        "roofline": roofline, "cpu_baseline": cpu, "spmv": spmv, "ceiling": ceiling, "kernels": kern,
-        "kernel_src": kernel_source_hash(), **extras, "sweep": sweep,
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"poisson16 n={A.rows}: row lengths max(1,Poisson(16)), distinct uniform columns, "
+                               f"N(0,1) values and x, seed 0", "rows": A.rows, "nnz": A.nnz,
+                   "value_is": "SpMV beta+ GB/s (Eq. 6.1) in the timed steps; a step is CSR->CMRS sorted + SpMV + "
+                               "CMRS->CSR"},
+        "roofline": roofline, "cpu_baseline": cpu,
+        "spmv": {"f64": {k: spmv64[k] for k in ("height", "schedule", "ms", "gbs_plus", "eta_plus", "eta_minus",
+                                                "gflops", "cold_ms", "cold_eta_plus")},
+                 "f32": {k: spmv32[k] for k in ("height", "schedule", "ms", "gbs_plus", "eta_plus", "eta_minus",
+                                                "gflops", "cold_ms", "cold_eta_plus")}},
+        "step": {"f64": {k: step64[k] for k in ("ms", "gbs", "calls")},
+                 "f32": {k: step32[k] for k in ("ms", "gbs")},
+                 "kernels_f64_ms": {k: v["ms"] for k, v in step64["kernels"].items()}},
+        "ceiling": ceiling, "extras": extras,
     }
-    print(json.dumps(out), flush=True)
+    detail = dict(res)
+    detail.update({"sweep": sweep, "kernel_src": kernel_source_hash(), "step_detail": {"f64": step64, "f32": step32},
+                   "spmv_detail": {"f64": spmv64, "f32": spmv32}})
+    path = args.detail or os.path.join(ROOT, "gpurun_out", "bench_detail.json")
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        with open(path, "w") as f:
+            json.dump(detail, f, indent=1)
+        res["detail_file"] = os.path.relpath(path, ROOT)
+    except OSError as e:
+        log(f"detail file not written: {e}")
+    print(compact_line(res), flush=True)
 
 
 if __name__ == "__main__":

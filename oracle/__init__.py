@@ -33,13 +33,19 @@ def build(force: bool = True) -> str:
     return _LIB_PATH
 
 
-def _load():
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(_LIB_PATH):
-        build(force=True)
-    lib = ctypes.CDLL(_LIB_PATH)
+def build_baseline(out_dir: str) -> str:
+    """Compile the same C source for the CPU-baseline timing: -O3
+    -march=native (for the host it runs on, so call it there) and -fopenmp
+    for ora_csr_spmv_par; still -ffp-contract=off, so results are unchanged.
+    Returns the path of the shared library."""
+    os.makedirs(out_dir, exist_ok=True)
+    path = os.path.join(out_dir, "liboracle_baseline%d.so" % os.getpid())
+    subprocess.check_call(["gcc", "-O3", "-march=native", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
+                           "-fopenmp", "-fPIC", "-shared", "-o", path, _SRC, "-lm"])
+    return path
+
+
+def _bind(lib):
     i32, u32p, i32p, vp = ctypes.c_int32, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p
     dp = ctypes.POINTER(ctypes.c_double)
     lib.ora_num_strips.argtypes = [i32, i32]
@@ -48,6 +54,8 @@ def _load():
     lib.ora_bits_for_height.restype = i32
     lib.ora_csr_spmv.argtypes = [i32, i32p, i32p, dp, dp, dp]
     lib.ora_csr_spmv.restype = None
+    lib.ora_csr_spmv_par.argtypes = [i32, i32p, i32p, dp, dp, dp, i32]
+    lib.ora_csr_spmv_par.restype = i32
     lib.ora_csr_absmv.argtypes = [i32, i32p, i32p, dp, dp, dp]
     lib.ora_csr_absmv.restype = None
     lib.ora_csr_to_dense.argtypes = [i32, i32, i32p, i32p, dp, dp]
@@ -58,8 +66,20 @@ def _load():
     lib.ora_csr_to_cmrs.restype = i32
     lib.ora_cmrs_to_csr.argtypes = [i32, i32, i32, i32, i32p, u32p, vp, i32, i32p, i32p, vp]
     lib.ora_cmrs_to_csr.restype = i32
-    _lib = lib
     return lib
+
+
+def _load(path: str | None = None):
+    """The oracle library (the test build), or the library at ``path``."""
+    global _lib
+    if path is not None:
+        return _bind(ctypes.CDLL(path))
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        build(force=True)
+    _lib = _bind(ctypes.CDLL(_LIB_PATH))
+    return _lib
 
 
 def _p(a, ct):
@@ -82,15 +102,28 @@ def bits_for_height(height: int) -> int:
     return int(_load().ora_bits_for_height(height))
 
 
-def csr_spmv(row_ptr, col_ind, val, x) -> np.ndarray:
+def csr_spmv(row_ptr, col_ind, val, x, lib=None) -> np.ndarray:
     """y = A x in fp64, serial CRS order, sum from +0.0."""
-    lib = _load()
+    lib = lib or _load()
     row_ptr, col_ind, val, x = _i32(row_ptr), _i32(col_ind), _f64(val), _f64(x)
     rows = row_ptr.size - 1
     y = np.empty(rows, dtype=np.float64)
     lib.ora_csr_spmv(rows, _p(row_ptr, ctypes.c_int32), _p(col_ind, ctypes.c_int32),
                      _p(val, ctypes.c_double), _p(x, ctypes.c_double), _p(y, ctypes.c_double))
     return y
+
+
+def csr_spmv_par(row_ptr, col_ind, val, x, threads: int, lib=None):
+    """ora_csr_spmv_par: the same y over nnz-balanced row ranges on
+    ``threads`` OpenMP threads (lib: a handle from _load(build_baseline(..)));
+    returns (y, threads used)."""
+    lib = lib or _load()
+    row_ptr, col_ind, val, x = _i32(row_ptr), _i32(col_ind), _f64(val), _f64(x)
+    rows = row_ptr.size - 1
+    y = np.empty(rows, dtype=np.float64)
+    used = lib.ora_csr_spmv_par(rows, _p(row_ptr, ctypes.c_int32), _p(col_ind, ctypes.c_int32),
+                                _p(val, ctypes.c_double), _p(x, ctypes.c_double), _p(y, ctypes.c_double), threads)
+    return y, int(used)
 
 
 def csr_absmv(row_ptr, col_ind, val, x) -> np.ndarray:

@@ -12,8 +12,10 @@
  * contraction), so every multiply and every add rounds separately in IEEE
  * binary64.
  *
- * Functions (all serial, no blocking, no reordering):
+ * Functions (serial except ora_csr_spmv_par; no blocking, no reordering):
  *   ora_csr_spmv       y = A x over CRS, Sec. 2.1 and 2.3
+ *   ora_csr_spmv_par   the same product, rows split into nnz-balanced ranges
+ *                      over OpenMP threads (CPU-baseline timing only)
  *   ora_csr_absmv      (|A||x|)_i, the scale of the componentwise error bound
  *   ora_csr_to_dense   COO/CRS scatter into a dense array (duplicates add)
  *   ora_dense_matvec   row-major dense matvec (brute force for tiny cases)
@@ -26,6 +28,9 @@
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* Number of strips: ceil(rows / height), Sec. 3. */
 int32_t ora_num_strips(int32_t rows, int32_t height)
@@ -61,6 +66,51 @@ void ora_csr_spmv(int32_t rows, const int32_t *row_ptr, const int32_t *col_ind,
         }
         y[i] = s;
     }
+}
+
+/* The same product with the rows cut into nthreads contiguous ranges of
+ * about nnz/nthreads entries each (range t starts at the first row whose
+ * RowPtr reaches t*nnz/nthreads), one range per OpenMP thread.  Every row is
+ * summed exactly as in ora_csr_spmv, so the result is identical bit for bit;
+ * only the CPU-baseline timing uses it.  Without -fopenmp it runs serially.
+ * Returns the number of threads that ran. */
+int32_t ora_csr_spmv_par(int32_t rows, const int32_t *row_ptr, const int32_t *col_ind,
+                         const double *val, const double *x, double *y, int32_t nthreads)
+{
+    if (nthreads < 1) nthreads = 1;
+    int32_t used = 1;
+    const int64_t nnz = rows > 0 ? (int64_t)row_ptr[rows] : 0;
+#pragma omp parallel num_threads(nthreads)
+    {
+        int32_t t = 0, nt = 1;
+#ifdef _OPENMP
+        t = (int32_t)omp_get_thread_num();
+        nt = (int32_t)omp_get_num_threads();
+#pragma omp single
+        used = nt;
+#endif
+        /* first row of range t: lower bound of t*nnz/nt in RowPtr */
+        int32_t bounds[2];
+        for (int32_t e = 0; e < 2; e++) {
+            const int64_t target = nnz * (int64_t)(t + e) / nt;
+            int32_t lo = 0, hi = rows;
+            while (lo < hi) {
+                const int32_t mid = lo + (hi - lo) / 2;
+                if ((int64_t)row_ptr[mid] < target) lo = mid + 1; else hi = mid;
+            }
+            bounds[e] = (t + e == nt) ? rows : lo;
+        }
+        if (t == 0) bounds[0] = 0;
+        for (int32_t i = bounds[0]; i < bounds[1]; i++) {
+            double s = 0.0;
+            for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; k++) {
+                double p = val[k] * x[col_ind[k]];
+                s = s + p;
+            }
+            y[i] = s;
+        }
+    }
+    return used;
 }
 
 /* (|A||x|)_i = sum_k |Val[k]| * |x[ColInd[k]]|, the scale in the

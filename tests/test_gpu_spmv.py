@@ -210,17 +210,76 @@ def c2x(c2):
     return synth.normal_vector(c2.cols, seed=1)
 
 
+class Bounds:
+    """Oracle references and elementwise tolerances of one workload, computed
+    once: fp64 4 k u |A||x|; fp32 / bf16 the arithmetic bound on the rounded
+    inputs and the total bound against the fp64 data (as assert_low_bound)."""
+
+    def __init__(self, A, x64):
+        self.A, self.x64 = A, x64
+        self.k = np.diff(A.row_ptr).astype(np.float64)
+        self.absmv = oracle.csr_absmv(A.row_ptr, A.col_ind, A.val, x64)
+        self.yref = oracle.csr_spmv(A.row_ptr, A.col_ind, A.val, x64)
+        self._low = {}
+
+    def check(self, y, dtype, what=""):
+        A = self.A
+        if dtype == "f64":
+            tol = 4.0 * self.k * U64 * self.absmv
+            bad = np.nonzero(np.abs(y - self.yref) > tol)[0]
+            assert bad.size == 0, f"{what}: {bad.size} rows out of the fp64 bound, first {bad[:5]}"
+        else:
+            if dtype not in self._low:
+                hv = G.host_vals(A.val, dtype)
+                v64 = G.vals_as_f64(hv, dtype)
+                xs = synth.round_to_f32(self.x64).astype(np.float64)
+                self._low[dtype] = (oracle.csr_spmv(A.row_ptr, A.col_ind, v64, xs),
+                                    4.0 * self.k * U32 * oracle.csr_absmv(A.row_ptr, A.col_ind, v64, xs))
+            yr, tr = self._low[dtype]
+            assert np.all(np.abs(y - yr) <= tr), f"{what}: arithmetic bound on rounded inputs"
+            rep = U16 if dtype == "bf16" else 0.0
+            tol = 2.0 * (rep + (self.k + 2) * U32) * self.absmv
+            assert np.all(np.abs(y - self.yref) <= tol), f"{what}: total bound against fp64 data"
+        empty = self.k == 0
+        assert np.all(y[empty] == 0) and not np.signbit(y[empty]).any()
+
+
+@pytest.fixture(scope="module")
+def c2b(c2, c2x):
+    return Bounds(c2, c2x)
+
+
 @pytest.mark.parametrize("height", [1, 2, 4, 8, 16, 32])
-def test_c2_full_fp64(C, c2, c2x, height):
-    for variant in ("auto", "lds", "reg", "group_nt"):
+def test_c2_full_fp64(C, c2, c2x, c2b, height):
+    """Every one-wave and strip-group variant the benchmark sweeps, at full
+    size (one wave per strip with non-temporal loads included)."""
+    for variant in ("auto", "lds", "lds_nt", "reg", "group_nt"):
         y, _, _ = run(C, c2, c2x, height, sort=True, variant=variant)
-        assert_fp64_bound(c2, c2x, y)
+        c2b.check(y, "f64", f"h={height} {variant}")
 
 
-@pytest.mark.parametrize("height", [1, 8, 32])
-def test_c2_full_fp32(C, c2, c2x, height):
-    y, hv, xs = run(C, c2, c2x, height, "f32", sort=True)
-    assert_low_bound(c2, hv, "f32", xs, c2x, y)
+@pytest.mark.parametrize("height", [1, 2, 4, 8, 16, 32])
+def test_c2_full_fp32(C, c2, c2x, c2b, height):
+    for variant in ("auto", "lds", "lds_nt"):
+        y, _, _ = run(C, c2, c2x, height, "f32", sort=True, variant=variant)
+        c2b.check(y, "f32", f"h={height} {variant}")
+
+
+@pytest.mark.parametrize("height", [1, 2, 4, 8, 16, 32])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_c2_full_colblock_concurrent(C, c2, c2x, c2b, height, dtype):
+    """The concurrent column-blocked schedule with 4 and 8 blocks at every
+    height (the benchmark's and the selector's colblock classes), full size:
+    the launcher picks its group width from the run length, so every width
+    these heights reach on this matrix is exercised."""
+    rp, ci, v, _ = G.upload(c2, dtype)
+    M = C.from_csr(rp, ci, v, c2.cols, height, sort=True)
+    xt, _ = G.xy_vector(c2x, dtype)
+    for nb in (4, 8):
+        plan = C.colblock_plan(M, nb)
+        y = C.spmv_colblock(M, plan, xt, schedule="concurrent")
+        torch.cuda.synchronize()
+        c2b.check(y.cpu().numpy().astype(np.float64), dtype, f"h={height} nb={nb}")
 
 
 @pytest.fixture(scope="module")
@@ -228,15 +287,30 @@ def c3():
     return synth.zipf_clustered(2_000_000, seed=0)
 
 
+@pytest.fixture(scope="module")
+def c3b(c3):
+    return Bounds(c3, synth.uniform_vector(c3.cols, seed=1))
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
-def test_c3_full(C, c3, dtype):
-    x = synth.uniform_vector(c3.cols, seed=1)
-    for h, variant in ((4, "auto"), (8, "auto"), (8, "group_nt"), (8, "lds")):
+def test_c3_full(C, c3, c3b, dtype):
+    x = c3b.x64
+    for h, variant in ((4, "auto"), (8, "auto"), (16, "auto"), (8, "group_nt"), (8, "lds"), (16, "lds_nt")):
         y, hv, xs = run(C, c3, x, h, dtype, sort=True, variant=variant)
-        if dtype == "f64":
-            assert_fp64_bound(c3, x, y)
-        else:
-            assert_low_bound(c3, hv, dtype, xs, x, y)
+        c3b.check(y, dtype, f"h={h} {variant}")
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_c3_full_colblock_concurrent(C, c3, c3b, dtype):
+    rp, ci, v, _ = G.upload(c3, dtype)
+    xt, _ = G.xy_vector(c3b.x64, dtype)
+    for h in (4, 16):
+        M = C.from_csr(rp, ci, v, c3.cols, h, sort=True)
+        for nb in (4, 8):
+            plan = C.colblock_plan(M, nb)
+            y = C.spmv_colblock(M, plan, xt, schedule="concurrent")
+            torch.cuda.synchronize()
+            c3b.check(y.cpu().numpy().astype(np.float64), dtype, f"h={h} nb={nb}")
 
 
 def run_colblock(C, A, x64, height, nb, dtype="f64", variant="auto", schedule="passes"):
