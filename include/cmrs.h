@@ -220,6 +220,29 @@ cmrs_status_t cmrs_spmv_colblock(const cmrs_mat_t *A, const void *x, void *y, cm
                                  int32_t schedule, void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /*
+ * The concurrent column-blocked product without a caller workspace, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * kernels and results as cmrs_spmv_colblock(..., CMRS_COLBLOCK_CONCURRENT,
+ * ...), bit for bit; the col_blocks * rows partial sums go to a scratch
+ * array of CMRS_NOALLOC_SCRATCH_BYTES that the library holds in device
+ * memory (one per GPU, alive until the process ends; its address is looked
+ * up on the first call on each device, with that device current).  Nothing
+ * is allocated and nothing needs clearing: every partial is written before
+ * it is read.  All calls on one GPU share that GPU's scratch, so calls that
+ * may overlap on one GPU (other streams, other host threads) race and must
+ * be ordered by the caller.  Errors as cmrs_spmv_colblock, plus
+ * CMRS_ERR_WORKSPACE when cmrs_spmv_colblock_workspace(A, col_blocks,
+ * CMRS_COLBLOCK_CONCURRENT) exceeds CMRS_NOALLOC_SCRATCH_BYTES (e.g. fp64
+ * values with 4 blocks: rows <= 2^20), and CMRS_ERR_DEVICE if the scratch
+ * address cannot be obtained.  col_blocks == 1 runs the plain product.
+ */
+#define CMRS_NOALLOC_SCRATCH_BYTES (32u << 20)
+cmrs_status_t cmrs_spmv_colblock_noalloc(const cmrs_mat_t *A, const void *x, void *y, cmrs_dtype_t xy_dtype,
+                                         int32_t variant, int32_t col_blocks, const int32_t *split,
+                                         size_t split_bytes, hipStream_t stream);
+
+/*
  * Products with several right-hand sides, Y = A X (the problem statement
  * y = A x of Sec. 2.1 for nrhs vectors at once; each loaded value and packed
  * word serves all of them).

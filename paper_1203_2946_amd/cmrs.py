@@ -67,6 +67,9 @@ lib.cmrs_colblock_plan.restype = ctypes.c_int
 lib.cmrs_spmv_colblock_workspace.argtypes, lib.cmrs_spmv_colblock_workspace.restype = [_DP, _i32, _i32], _sz
 lib.cmrs_spmv_colblock.argtypes = [_DP, _vp, _vp, ctypes.c_int, _i32, _i32, _vp, _sz, _i32, _vp, _sz, _vp]
 lib.cmrs_spmv_colblock.restype = ctypes.c_int
+lib.cmrs_spmv_colblock_noalloc.argtypes = [_DP, _vp, _vp, ctypes.c_int, _i32, _i32, _vp, _sz, _vp]
+lib.cmrs_spmv_colblock_noalloc.restype = ctypes.c_int
+NOALLOC_SCRATCH_BYTES = 32 << 20  # CMRS_NOALLOC_SCRATCH_BYTES
 lib.cmrs_calib_stream_read.argtypes = [_vp, _vp, _i32, ctypes.c_int, _i32, _vp, _vp]
 lib.cmrs_calib_stream_read.restype = ctypes.c_int
 lib.cmrs_calib_gather.argtypes = [_vp, ctypes.c_int64, _vp, ctypes.c_int, _vp, _vp]
@@ -120,6 +123,7 @@ lib.cmrs_last_error.argtypes, lib.cmrs_last_error.restype = [], ctypes.c_char_p
 EXPORTED = ["cmrs_abi_version", "cmrs_num_strips", "cmrs_bits_for_height", "cmrs_from_csr_workspace",
             "cmrs_from_csr", "cmrs_to_csr_workspace", "cmrs_to_csr", "cmrs_spmv", "cmrs_validate_csr",
             "cmrs_colblock_plan_bytes", "cmrs_colblock_plan", "cmrs_spmv_colblock_workspace", "cmrs_spmv_colblock",
+            "cmrs_spmv_colblock_noalloc",
             "cmrs_spmm", "cmrs_spmm_plan_bytes", "cmrs_spmm_plan", "cmrs_spmm_batched",
             "cmrs_padded_bits", "cmrs_padded_plan_workspace", "cmrs_padded_plan", "cmrs_padded_from_csr",
             "cmrs_padded_spmv",
@@ -327,6 +331,28 @@ def spmv_colblock(A: CmrsMatrix, plan: ColblockPlan, x: torch.Tensor, out: torch
                                 _ptr(plan.split), plan.nbytes, COLBLOCK_SCHEDULES[schedule],
                                 _ptr(workspace) if wsb else None, wsb, _stream(stream))
     _check(st, "cmrs_spmv_colblock")
+    return y
+
+
+def spmv_colblock_noalloc(A: CmrsMatrix, plan: ColblockPlan, x: torch.Tensor, out: torch.Tensor | None = None,
+                          variant: int | str = SPMV_AUTO, stream=None) -> torch.Tensor:
+    """The concurrent column-blocked y = A x with its partial sums in the
+    library's static device scratch (cmrs_spmv_colblock_noalloc): allocates
+    nothing when ``out`` is given."""
+    if isinstance(variant, str):
+        variant = VARIANTS[variant]
+    xdt = torch.float64 if A.val.dtype == torch.float64 else torch.float32
+    _dev(x, "x", xdt)
+    if x.numel() != A.cols:
+        raise ValueError(f"x has {x.numel()} entries, the matrix {A.cols} columns")
+    y = out if out is not None else torch.empty(A.rows, dtype=xdt, device=x.device)
+    _dev(y, "y", xdt)
+    if y.numel() != A.rows:
+        raise ValueError("y has the wrong length")
+    d = A.desc()
+    st = lib.cmrs_spmv_colblock_noalloc(ctypes.byref(d), _ptr(x), _ptr(y), _DT[xdt], int(variant), plan.col_blocks,
+                                        _ptr(plan.split), plan.nbytes, _stream(stream))
+    _check(st, "cmrs_spmv_colblock_noalloc")
     return y
 
 

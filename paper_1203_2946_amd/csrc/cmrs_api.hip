@@ -239,6 +239,28 @@ cmrs_status_t cmrs_spmv_colblock(const cmrs_mat_t* A, const void* x, void* y, cm
                     "cmrs_spmv_colblock");
 }
 
+cmrs_status_t cmrs_spmv_colblock_noalloc(const cmrs_mat_t* A, const void* x, void* y, cmrs_dtype_t xy_dtype,
+                                         int32_t variant, int32_t col_blocks, const int32_t* split,
+                                         size_t split_bytes, hipStream_t stream) {
+    g_last_error[0] = 0;
+    cmrs_status_t st = check_spmv_args(A, x, y, xy_dtype, variant);
+    if (st != CMRS_OK || A->rows == 0) return st;
+    st = check_colblock(A, col_blocks, split, split_bytes);
+    if (st != CMRS_OK) return st;
+    const size_t need = cmrs_spmv_colblock_workspace(A, col_blocks, CMRS_COLBLOCK_CONCURRENT);
+    if (need > CMRS_NOALLOC_SCRATCH_BYTES)
+        return fail(CMRS_ERR_WORKSPACE, "%zu bytes of partial sums needed, the static scratch holds %u", need,
+                    CMRS_NOALLOC_SCRATCH_BYTES);
+    void* scratch = nullptr;
+    if (need > 0) {
+        st = from_hip(cmrs::noalloc_scratch(&scratch), "cmrs_spmv_colblock_noalloc (scratch address)");
+        if (st != CMRS_OK) return st;
+    }
+    return from_hip(cmrs::launch_spmv_colblock(A, x, y, variant, col_blocks, split, CMRS_COLBLOCK_CONCURRENT, scratch,
+                                               stream),
+                    "cmrs_spmv_colblock_noalloc");
+}
+
 static bool dtype_pair_ok(cmrs_dtype_t val, cmrs_dtype_t xy) {
     return (val == CMRS_R64F && xy == CMRS_R64F) || (val == CMRS_R32F && xy == CMRS_R32F) ||
            (val == CMRS_R16BF && xy == CMRS_R32F);

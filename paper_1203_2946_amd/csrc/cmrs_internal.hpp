@@ -70,6 +70,9 @@ int resolve_spmv_variant(const cmrs_mat_t* A, int variant);
 hipError_t launch_colblock_plan(const cmrs_mat_t* A, int nb, int bw, int* split, hipStream_t stream);
 hipError_t launch_spmv_colblock(const cmrs_mat_t* A, const void* x, void* y, int variant, int nb, const int* split,
                                 int schedule, void* workspace, hipStream_t stream);
+// Device address of this GPU's CMRS_NOALLOC_SCRATCH_BYTES scratch array
+// (looked up once per device, with that device current).
+hipError_t noalloc_scratch(void** ptr);
 
 hipError_t launch_calib_stream(const void* word, const void* val, int32_t nnz, cmrs_dtype_t dtype,
                                int32_t lds_words_per_lane, double* sink, hipStream_t stream);

@@ -25,6 +25,8 @@
 //
 // Workgroups hold 4 waves (4 strips); workgroup ids are renumbered so that each
 // XCD processes one contiguous range of strips.
+#include <mutex>
+
 #include "cmrs_device.hpp"
 #include "cmrs_internal.hpp"
 
@@ -554,6 +556,37 @@ hipError_t launch_colblock_plan(const cmrs_mat_t* A, int nb, int bw, int* split,
     hipLaunchKernelGGL(colblock_plan_kernel, dim3(blocks), dim3(256), 0, stream, strips, A->bits, bw, nb,
                        A->strip_ptr, A->col_word, split);
     return hipGetLastError();
+}
+
+// Scratch of the allocation-free concurrent column-blocked product
+// (cmrs_spmv_colblock_noalloc): the nb * rows partial sums live in this
+// file-scope array instead of a caller workspace.  Every GPU the library runs
+// on holds its own copy at its own address until the process ends; host code
+// must use that address (from hipGetSymbolAddress), never the array's name,
+// which on the host is only a stand-in for the symbol.
+static __device__ __align__(256) unsigned char scratch[CMRS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(void** ptr) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (p == nullptr) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_spmv_colblock(const cmrs_mat_t* A, const void* x, void* y, int variant, int nb,

@@ -217,3 +217,23 @@ def test_sizes_above_max_index_rejected(C):
     d = _mat(C, rows=big)
     assert C.lib.cmrs_spmv(ctypes.byref(d), FAKE + 4096, FAKE + 8192, 0, 0, None) == 2
     assert C.lib.cmrs_validate_csr(big, 4, 4, FAKE, FAKE, FAKE, None) == 2
+
+
+def test_colblock_noalloc_host_checks(C):
+    """The allocation-free column-blocked product refuses, before any device
+    call, partial sums beyond its static scratch and the same bad arguments
+    as cmrs_spmv_colblock."""
+    big = 1 << 21                                  # fp64, 4 blocks: 4 * 2^21 * 8 B = 64 MiB > 32 MiB
+    d = _mat(C, rows=big, cols=big, nnz=4, height=4, sorted=1)
+    assert C.lib.cmrs_spmv_colblock_noalloc(ctypes.byref(d), FAKE, FAKE + (1 << 30), 0, 0, 4, FAKE,
+                                            1 << 30, None) == 5
+    assert "scratch" in C.lib.cmrs_last_error().decode()
+    assert C.lib.cmrs_spmv_colblock_workspace(ctypes.byref(d), 4, 1) == 4 * big * 8 > C.NOALLOC_SCRATCH_BYTES
+    ok = _mat(C, rows=1 << 20, cols=1 << 20, nnz=4, height=4, sorted=1)
+    assert C.lib.cmrs_spmv_colblock_workspace(ctypes.byref(ok), 4, 1) == C.NOALLOC_SCRATCH_BYTES
+    unsorted = _mat(C, sorted=0)
+    assert C.lib.cmrs_spmv_colblock_noalloc(ctypes.byref(unsorted), FAKE, FAKE + 4096, 0, 0, 4, FAKE, 64, None) == 1
+    small = _mat(C, sorted=1)
+    assert C.lib.cmrs_spmv_colblock_noalloc(ctypes.byref(small), FAKE, FAKE + 4096, 0, 0, 4, None, 0, None) == 5
+    assert C.lib.cmrs_spmv_colblock_noalloc(ctypes.byref(small), FAKE, FAKE + 4096, 0, 0, 65, FAKE, 64, None) == 1
+    assert C.lib.cmrs_spmv_colblock_noalloc(ctypes.byref(small), FAKE, FAKE + 8, 0, 0, 4, FAKE, 64, None) == 1
