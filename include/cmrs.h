@@ -190,7 +190,7 @@ cmrs_status_t cmrs_spmv(const cmrs_mat_t *A, const void *x, void *y, cmrs_dtype_
  * col_blocks-1, the index of the first entry of strip s in block b:
  *   split[s * (col_blocks - 1) + b - 1]      (int32, device)
  * Every run is processed exactly as cmrs_spmv processes a strip; the gathers
- * of one run touch only 1/col_blocks of x.  Two schedules:
+ * of one run touch only 1/col_blocks of x.  Three schedules:
  *   CMRS_COLBLOCK_PASSES      col_blocks launches, pass b adds run b of every
  *                             strip to y (pass 0 overwrites y); no workspace.
  *   CMRS_COLBLOCK_CONCURRENT  one launch; workgroup w takes column block
@@ -201,6 +201,13 @@ cmrs_status_t cmrs_spmv(const cmrs_mat_t *A, const void *x, void *y, cmrs_dtype_
  *                             for fp64 values, fp32 otherwise), then a second
  *                             kernel adds the col_blocks partials of each row
  *                             in block order.
+ *   CMRS_COLBLOCK_PHASED      one launch, no workspace: each wave owns whole
+ *                             strips (a strip group) and walks block 0 of
+ *                             all of them, then block 1, ..., adding into
+ *                             the same per-lane partial sums, and writes y
+ *                             once; the waves of an XCD move through the
+ *                             blocks together, so they gather from about one
+ *                             block of x at a time.
  * Results obey the same error bound as cmrs_spmv (the products of a row are
  * summed in a different order) and are deterministic.
  *   col_blocks   1 .. 64; 1 means no blocking (plan of zero bytes).
@@ -211,6 +218,7 @@ cmrs_status_t cmrs_spmv(const cmrs_mat_t *A, const void *x, void *y, cmrs_dtype_
  */
 #define CMRS_COLBLOCK_PASSES 0
 #define CMRS_COLBLOCK_CONCURRENT 1
+#define CMRS_COLBLOCK_PHASED 2
 size_t cmrs_colblock_plan_bytes(const cmrs_mat_t *A, int32_t col_blocks);
 cmrs_status_t cmrs_colblock_plan(const cmrs_mat_t *A, int32_t col_blocks, int32_t *split, size_t split_bytes,
                                  hipStream_t stream);
@@ -218,6 +226,54 @@ size_t cmrs_spmv_colblock_workspace(const cmrs_mat_t *A, int32_t col_blocks, int
 cmrs_status_t cmrs_spmv_colblock(const cmrs_mat_t *A, const void *x, void *y, cmrs_dtype_t xy_dtype,
                                  int32_t variant, int32_t col_blocks, const int32_t *split, size_t split_bytes,
                                  int32_t schedule, void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * Split schedule for strips of very different lengths (skewed rows).  The
+ * paper sets matrices with very long rows aside for special algorithms
+ * (Sec. 6.2); Algorithm 1 would give each such strip to one wave, which then
+ * sets the time of the whole product.  Here every strip with more than
+ * long_len stored entries is "heavy": a plan cuts it into chunks of at most
+ * chunk_len consecutive entries, chunk waves compute the chunks' row sums
+ * (each as Algorithm 1 computes a strip) while all other strips run as
+ * strip groups (CMRS_SPMV_GROUP_NT), and a second small launch adds each
+ * split strip's chunk sums in chunk order and writes its rows.  y is
+ * overwritten, the error bound of cmrs_spmv holds, results are
+ * deterministic.
+ *
+ * cmrs_spmv_split_plan_bytes: device bytes of the plan buffer (0 for an
+ *   invalid matrix or negative long_len / chunk_len).  long_len 0 picks
+ *   16 entries per lane of the strip-group width, chunk_len 0 picks 1024.
+ * cmrs_spmv_split_plan: fills *plan (host struct) and, asynchronously on
+ *   `stream`, the caller's device buffer `buf` (16-byte aligned, at least
+ *   cmrs_spmv_split_plan_bytes): the heavy-strip and chunk lists and room
+ *   for the chunk sums.  It reads only A's
+ *   strip_ptr (device) and needs no synchronisation, so it may run in the
+ *   same stream before each product; rebuild it when strip_ptr changes.
+ * cmrs_spmv_split: y = A x with the plan.  The product writes the chunk
+ *   sums into the plan buffer, so products with one plan must not overlap.
+ *   Dtypes as cmrs_spmv.
+ * Errors: CMRS_ERR_INVALID_VALUE for a bad matrix, negative long_len /
+ *   chunk_len, a plan built for another matrix shape or inconsistent fields,
+ *   NULL or overlapping x / y; CMRS_ERR_WORKSPACE for a NULL, misaligned or
+ *   short buffer; CMRS_ERR_NOT_SUPPORTED for a dtype pair other than
+ *   cmrs_spmv's; CMRS_ERR_DEVICE if a launch fails.  *plan is written only on
+ *   success.
+ */
+typedef struct {
+    int32_t rows, nnz, height;  /* shape of the matrix the plan was built for     */
+    int32_t group;              /* lanes per strip of the strip-group waves       */
+    int32_t long_len;           /* strips with more entries are split             */
+    int32_t chunk_len;          /* entries per chunk, at most                     */
+    int32_t max_heavy;          /* capacity of the heavy-strip list               */
+    int32_t max_chunks;         /* capacity of the chunk list                     */
+    void *buf;                  /* the caller's device buffer                     */
+    size_t bytes;
+} cmrs_split_plan_t;
+size_t cmrs_spmv_split_plan_bytes(const cmrs_mat_t *A, int32_t long_len, int32_t chunk_len);
+cmrs_status_t cmrs_spmv_split_plan(const cmrs_mat_t *A, int32_t long_len, int32_t chunk_len, void *buf,
+                                   size_t bytes, cmrs_split_plan_t *plan, hipStream_t stream);
+cmrs_status_t cmrs_spmv_split(const cmrs_mat_t *A, const cmrs_split_plan_t *plan, const void *x, void *y,
+                              cmrs_dtype_t xy_dtype, hipStream_t stream);
 
 /*
  * The concurrent column-blocked product without a caller workspace, for

@@ -70,6 +70,21 @@ lib.cmrs_spmv_colblock.restype = ctypes.c_int
 lib.cmrs_spmv_colblock_noalloc.argtypes = [_DP, _vp, _vp, ctypes.c_int, _i32, _i32, _vp, _sz, _vp]
 lib.cmrs_spmv_colblock_noalloc.restype = ctypes.c_int
 NOALLOC_SCRATCH_BYTES = 32 << 20  # CMRS_NOALLOC_SCRATCH_BYTES
+
+
+class SplitPlanStruct(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int32), ("nnz", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("group", ctypes.c_int32), ("long_len", ctypes.c_int32), ("chunk_len", ctypes.c_int32),
+                ("max_heavy", ctypes.c_int32), ("max_chunks", ctypes.c_int32), ("buf", ctypes.c_void_p),
+                ("bytes", ctypes.c_size_t)]
+
+
+lib.cmrs_spmv_split_plan_bytes.argtypes = [_DP, _i32, _i32]
+lib.cmrs_spmv_split_plan_bytes.restype = _sz
+lib.cmrs_spmv_split_plan.argtypes = [_DP, _i32, _i32, _vp, _sz, ctypes.POINTER(SplitPlanStruct), _vp]
+lib.cmrs_spmv_split_plan.restype = ctypes.c_int
+lib.cmrs_spmv_split.argtypes = [_DP, ctypes.POINTER(SplitPlanStruct), _vp, _vp, ctypes.c_int, _vp]
+lib.cmrs_spmv_split.restype = ctypes.c_int
 lib.cmrs_calib_stream_read.argtypes = [_vp, _vp, _i32, ctypes.c_int, _i32, _vp, _vp]
 lib.cmrs_calib_stream_read.restype = ctypes.c_int
 lib.cmrs_calib_gather.argtypes = [_vp, ctypes.c_int64, _vp, ctypes.c_int, _vp, _vp]
@@ -123,7 +138,7 @@ lib.cmrs_last_error.argtypes, lib.cmrs_last_error.restype = [], ctypes.c_char_p
 EXPORTED = ["cmrs_abi_version", "cmrs_num_strips", "cmrs_bits_for_height", "cmrs_from_csr_workspace",
             "cmrs_from_csr", "cmrs_to_csr_workspace", "cmrs_to_csr", "cmrs_spmv", "cmrs_validate_csr",
             "cmrs_colblock_plan_bytes", "cmrs_colblock_plan", "cmrs_spmv_colblock_workspace", "cmrs_spmv_colblock",
-            "cmrs_spmv_colblock_noalloc",
+            "cmrs_spmv_colblock_noalloc", "cmrs_spmv_split_plan_bytes", "cmrs_spmv_split_plan", "cmrs_spmv_split",
             "cmrs_spmm", "cmrs_spmm_plan_bytes", "cmrs_spmm_plan", "cmrs_spmm_batched",
             "cmrs_padded_bits", "cmrs_padded_plan_workspace", "cmrs_padded_plan", "cmrs_padded_from_csr",
             "cmrs_padded_spmv",
@@ -301,7 +316,7 @@ def colblock_plan(A: CmrsMatrix, col_blocks: int, stream=None) -> ColblockPlan:
     return ColblockPlan(col_blocks, split)
 
 
-COLBLOCK_SCHEDULES = {"passes": 0, "concurrent": 1}
+COLBLOCK_SCHEDULES = {"passes": 0, "concurrent": 1, "phased": 2}
 
 
 def spmv_colblock_workspace_bytes(A: CmrsMatrix, col_blocks: int, schedule: str = "passes") -> int:
@@ -353,6 +368,50 @@ def spmv_colblock_noalloc(A: CmrsMatrix, plan: ColblockPlan, x: torch.Tensor, ou
     st = lib.cmrs_spmv_colblock_noalloc(ctypes.byref(d), _ptr(x), _ptr(y), _DT[xdt], int(variant), plan.col_blocks,
                                         _ptr(plan.split), plan.nbytes, _stream(stream))
     _check(st, "cmrs_spmv_colblock_noalloc")
+    return y
+
+
+class SplitPlan:
+    """Plan of the split schedule: the device buffer and the filled struct."""
+
+    def __init__(self, buf: torch.Tensor, plan: SplitPlanStruct):
+        self.buf = buf
+        self.plan = plan
+
+
+def split_plan(A: CmrsMatrix, long_len: int = 0, chunk_len: int = 0, out: SplitPlan | None = None,
+               stream=None) -> SplitPlan:
+    """Heavy-strip plan of the split schedule (asynchronous; reads A's
+    strip_ptr).  ``out`` reuses the buffer of an earlier plan of A."""
+    d = A.desc()
+    nbytes = int(lib.cmrs_spmv_split_plan_bytes(ctypes.byref(d), long_len, chunk_len))
+    if nbytes == 0:
+        raise ValueError("invalid matrix or lengths (cmrs_spmv_split_plan_bytes returned 0)")
+    if out is not None and out.buf.numel() >= nbytes:
+        buf = out.buf
+    else:
+        buf = torch.empty(nbytes, dtype=torch.uint8, device=A.col_word.device)
+    plan = SplitPlanStruct()
+    st = lib.cmrs_spmv_split_plan(ctypes.byref(d), long_len, chunk_len, buf.data_ptr(), buf.numel(),
+                                  ctypes.byref(plan), _stream(stream))
+    _check(st, "cmrs_spmv_split_plan")
+    return SplitPlan(buf, plan)
+
+
+def spmv_split(A: CmrsMatrix, plan: SplitPlan, x: torch.Tensor, out: torch.Tensor | None = None,
+               stream=None) -> torch.Tensor:
+    """y = A x with the split schedule."""
+    xdt = torch.float64 if A.val.dtype == torch.float64 else torch.float32
+    _dev(x, "x", xdt)
+    if x.numel() != A.cols:
+        raise ValueError(f"x has {x.numel()} entries, the matrix {A.cols} columns")
+    y = out if out is not None else torch.empty(A.rows, dtype=xdt, device=x.device)
+    _dev(y, "y", xdt)
+    if y.numel() != A.rows:
+        raise ValueError("y has the wrong length")
+    d = A.desc()
+    st = lib.cmrs_spmv_split(ctypes.byref(d), ctypes.byref(plan.plan), _ptr(x), _ptr(y), _DT[xdt], _stream(stream))
+    _check(st, "cmrs_spmv_split")
     return y
 
 

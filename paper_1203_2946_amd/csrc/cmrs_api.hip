@@ -227,7 +227,7 @@ cmrs_status_t cmrs_spmv_colblock(const cmrs_mat_t* A, const void* x, void* y, cm
     if (st != CMRS_OK || A->rows == 0) return st;
     st = check_colblock(A, col_blocks, split, split_bytes);
     if (st != CMRS_OK) return st;
-    if (schedule != CMRS_COLBLOCK_PASSES && schedule != CMRS_COLBLOCK_CONCURRENT)
+    if (schedule != CMRS_COLBLOCK_PASSES && schedule != CMRS_COLBLOCK_CONCURRENT && schedule != CMRS_COLBLOCK_PHASED)
         return fail(CMRS_ERR_INVALID_VALUE, "unknown schedule %d", schedule);
     const size_t need = cmrs_spmv_colblock_workspace(A, col_blocks, schedule);
     if (need > 0 && (!workspace || workspace_bytes < need))
@@ -237,6 +237,62 @@ cmrs_status_t cmrs_spmv_colblock(const cmrs_mat_t* A, const void* x, void* y, cm
         return fail(CMRS_ERR_INVALID_VALUE, "workspace overlaps x or y");
     return from_hip(cmrs::launch_spmv_colblock(A, x, y, variant, col_blocks, split, schedule, workspace, stream),
                     "cmrs_spmv_colblock");
+}
+
+size_t cmrs_spmv_split_plan_bytes(const cmrs_mat_t* A, int32_t long_len, int32_t chunk_len) {
+    if (!A || long_len < 0 || chunk_len < 0) return 0;
+    if (check_mat(A) != CMRS_OK) return 0;
+    return cmrs::split_shape(A, long_len, chunk_len).total;
+}
+
+cmrs_status_t cmrs_spmv_split_plan(const cmrs_mat_t* A, int32_t long_len, int32_t chunk_len, void* buf,
+                                   size_t bytes, cmrs_split_plan_t* plan, hipStream_t stream) {
+    g_last_error[0] = 0;
+    cmrs_status_t st = check_mat(A);
+    if (st != CMRS_OK) return st;
+    if (long_len < 0 || chunk_len < 0)
+        return fail(CMRS_ERR_INVALID_VALUE, "long_len %d / chunk_len %d negative", long_len, chunk_len);
+    if (!plan) return fail(CMRS_ERR_INVALID_VALUE, "plan is NULL");
+    const cmrs::SplitShape sh = cmrs::split_shape(A, long_len, chunk_len);
+    if (!buf || bytes < sh.total || (reinterpret_cast<uintptr_t>(buf) & 15u))
+        return fail(CMRS_ERR_WORKSPACE, "plan buffer of %zu bytes (16-byte aligned) needed, %zu given", sh.total,
+                    bytes);
+    st = from_hip(cmrs::launch_split_plan(A, sh, buf, stream), "cmrs_spmv_split_plan");
+    if (st != CMRS_OK) return st;
+    plan->rows = A->rows;
+    plan->nnz = A->nnz;
+    plan->height = A->height;
+    plan->group = sh.group;
+    plan->long_len = sh.long_len;
+    plan->chunk_len = sh.chunk_len;
+    plan->max_heavy = sh.max_heavy;
+    plan->max_chunks = sh.max_chunks;
+    plan->buf = buf;
+    plan->bytes = bytes;
+    return CMRS_OK;
+}
+
+cmrs_status_t cmrs_spmv_split(const cmrs_mat_t* A, const cmrs_split_plan_t* plan, const void* x, void* y,
+                              cmrs_dtype_t xy_dtype, hipStream_t stream) {
+    g_last_error[0] = 0;
+    cmrs_status_t st = check_spmv_args(A, x, y, xy_dtype, CMRS_SPMV_AUTO);
+    if (st != CMRS_OK) return st;
+    if (!plan) return fail(CMRS_ERR_INVALID_VALUE, "plan is NULL");
+    if (plan->rows != A->rows || plan->nnz != A->nnz || plan->height != A->height)
+        return fail(CMRS_ERR_INVALID_VALUE, "plan built for rows=%d nnz=%d height=%d, matrix has %d/%d/%d", plan->rows,
+                    plan->nnz, plan->height, A->rows, A->nnz, A->height);
+    if (plan->long_len < 1 || plan->chunk_len < 1) return fail(CMRS_ERR_INVALID_VALUE, "corrupt plan");
+    const cmrs::SplitShape sh = cmrs::split_shape(A, plan->long_len, plan->chunk_len);
+    if (sh.group != plan->group || sh.max_heavy != plan->max_heavy || sh.max_chunks != plan->max_chunks)
+        return fail(CMRS_ERR_INVALID_VALUE, "corrupt plan");
+    if (!plan->buf || plan->bytes < sh.total || (reinterpret_cast<uintptr_t>(plan->buf) & 15u))
+        return fail(CMRS_ERR_WORKSPACE, "plan buffer NULL, misaligned or below %zu bytes", sh.total);
+    const size_t xs = cmrs::dtype_bytes(xy_dtype);
+    if (ranges_overlap(plan->buf, sh.total, y, xs * static_cast<size_t>(A->rows)) ||
+        ranges_overlap(plan->buf, sh.total, x, xs * static_cast<size_t>(A->cols)))
+        return fail(CMRS_ERR_INVALID_VALUE, "plan buffer overlaps x or y");
+    if (A->rows == 0) return CMRS_OK;
+    return from_hip(cmrs::launch_spmv_split(A, sh, plan->buf, x, y, stream), "cmrs_spmv_split");
 }
 
 cmrs_status_t cmrs_spmv_colblock_noalloc(const cmrs_mat_t* A, const void* x, void* y, cmrs_dtype_t xy_dtype,

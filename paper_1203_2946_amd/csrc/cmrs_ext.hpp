@@ -2,6 +2,7 @@
 // and batches, the padded layout of Sec. 6.7 and the learned selector.
 #pragma once
 
+#include <algorithm>
 #include <vector>
 
 #include "cmrs_internal.hpp"
@@ -59,6 +60,24 @@ hipError_t launch_padded_fill(int rows, int height, int bits, const int* row_ptr
                               const void* val_in, cmrs_dtype_t dtype, const int* strip_ptr, uint32_t* word_out,
                               void* val_out, hipStream_t stream);
 hipError_t launch_padded_spmv(const cmrs_mat_t* A, const void* x, void* y, hipStream_t stream);
+
+// Split schedule for skewed strips: a heavy strip's entry in the plan, one
+// chunk of it, and the plan's sizes and buffer layout.
+struct SplitHeavy {
+    int32_t strip, first, nchunks, pad;
+};
+struct SplitChunk {
+    int32_t heavy, lo, hi, pad;
+};
+constexpr int kSplitU = 8;  // entries per lane in flight (stream loads, then gathers)
+struct SplitShape {
+    int group, long_len, chunk_len, max_heavy, max_chunks;
+    size_t heavy_off, chunk_off, partial_off, total;
+};
+SplitShape split_shape(const cmrs_mat_t* A, int long_len, int chunk_len);
+hipError_t launch_split_plan(const cmrs_mat_t* A, const SplitShape& s, void* buf, hipStream_t stream);
+hipError_t launch_spmv_split(const cmrs_mat_t* A, const SplitShape& s, const void* buf, const void* x, void* y,
+                             hipStream_t stream);
 
 hipError_t launch_features(int rows, int cols, int nnz, const int* row_ptr, const int* col_ind, float* feat,
                            int* ws, hipStream_t stream);

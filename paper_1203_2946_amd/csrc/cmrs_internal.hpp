@@ -66,10 +66,15 @@ hipError_t launch_to_csr(const cmrs_mat_t* A, int32_t* row_ptr, int32_t* col_ind
 
 hipError_t launch_spmv(const cmrs_mat_t* A, const void* x, void* y, cmrs_dtype_t xy_dtype, int variant,
                        hipStream_t stream);
+// Lanes per strip of the strip-group SpMV: about 8 entries per lane for the
+// average strip, at least hb (next_pow2 of the height), a power of two <= 64.
+int spmv_group_width(int nnz, int strips, int hb);
 int resolve_spmv_variant(const cmrs_mat_t* A, int variant);
 hipError_t launch_colblock_plan(const cmrs_mat_t* A, int nb, int bw, int* split, hipStream_t stream);
 hipError_t launch_spmv_colblock(const cmrs_mat_t* A, const void* x, void* y, int variant, int nb, const int* split,
                                 int schedule, void* workspace, hipStream_t stream);
+hipError_t launch_spmv_phased(const cmrs_mat_t* A, const void* x, void* y, int nb, const int* split,
+                              hipStream_t stream);
 // Device address of this GPU's CMRS_NOALLOC_SCRATCH_BYTES scratch array
 // (looked up once per device, with that device current).
 hipError_t noalloc_scratch(void** ptr);

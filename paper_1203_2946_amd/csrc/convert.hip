@@ -364,6 +364,176 @@ __global__ __launch_bounds__(kConvThreads) __attribute__((amdgpu_waves_per_eu(8)
     }
 }
 
+// ------------------------------------------------------------------ tall strips
+
+// Sorted CSR -> CMRS for tall strips, one wave per strip of at most
+// kWave*E entries (longer strips go to the workspace lists).  The merge of
+// the group kernel costs log2(height) levels of binary searches; here an
+// entry's place comes from one bucketing pass instead, whatever the height:
+// entries fall into NB buckets of about equal width over the strip's column
+// range [cmin, cmax] (NB about n/4; the bucket is a multiply and a shift of
+// c - cmin, non-decreasing in c), a count per bucket (LDS atomics) and a
+// scan give each bucket's start, the
+// keys (word << 32 | position in strip) are scattered by bucket, and an
+// entry's place is its bucket's start plus the number of keys of its bucket
+// below its own.  Keys are unique and ordered as the reorder of Sec. 4
+// requires (column, then RowInStrip, then CSR order), so unsorted rows and
+// duplicates need no special path.  A strip whose largest bucket holds more
+// than kBucketMax keys (columns bunched at a few values far apart) is sorted
+// by a bitonic network over the same keys instead.
+constexpr int kBucketMax = 64;
+// The sorted conversion uses it from this height (next power of two) on, for
+// strips of at least kBucketMinMean entries on average: one wave per strip
+// costs more than the merge for short strips (measured).
+constexpr int kBucketMinHeight = 16;
+constexpr double kBucketMinMean = 320.0;
+
+template <int HB, int E, typename ET>
+__global__ __launch_bounds__(kConvThreads) void from_csr_bucket_kernel(
+    int rows, int strips, int height, int bits, int nnz, const int* __restrict__ row_ptr,
+    const int* __restrict__ col_ind, const ET* __restrict__ val_in, int* __restrict__ strip_ptr,
+    uint32_t* __restrict__ col_word, ET* __restrict__ val_out, int* __restrict__ ws_count,
+    int* __restrict__ ws_small, int* __restrict__ ws_big) {
+    constexpr int CAP = kWave * E;
+    constexpr int NBMAX = CAP / 4;
+    __shared__ uint64_t keys[kConvWaves][CAP];
+    __shared__ int bcnt[kConvWaves][NBMAX];
+    __shared__ int bstart[kConvWaves][NBMAX];
+    const int lane = lane_id();
+    const int wave = uniform(static_cast<int>(threadIdx.x) / kWave);
+    const int strip = xcd_logical_block(blockIdx.x, gridDim.x) * kConvWaves + wave;
+    if (strip >= strips) return;
+    const StripRows sr = load_strip_rows(strip, rows, height, row_ptr, lane);
+    const int n = sr.s1 - sr.s0;
+    if (lane == 0) {
+        strip_ptr[strip] = sr.s0;
+        if (strip == strips - 1) strip_ptr[strips] = nnz;
+    }
+    if (n > CAP) {
+        if (lane == 0) {
+            if (n <= kWaveSortCap)
+                ws_small[atomicAdd(&ws_count[0], 1)] = strip;
+            else
+                ws_big[atomicAdd(&ws_count[1], 1)] = strip;
+        }
+        return;
+    }
+    if (n == 0) return;
+    const int umax = uniform((n + kWave - 1) / kWave);
+    uint32_t wd[E];
+    ET v[E];
+    int cmin = INT_MAX, cmax = -1;
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+        wd[u] = 0u;
+        v[u] = ET(0);
+        if (u < umax) {
+            const int i = lane + kWave * u;
+            const int r = row_in_strip<HB>(sr.myrp, sr.s0 + i, 0);
+            if (i < n) {
+                const int c = col_ind[sr.s0 + i];
+                v[u] = val_in[sr.s0 + i];
+                wd[u] = (static_cast<uint32_t>(c) << bits) | static_cast<uint32_t>(r);
+                cmin = min(cmin, c);
+                cmax = max(cmax, c);
+            }
+        }
+    }
+#pragma unroll
+    for (int off = kWave / 2; off >= 1; off >>= 1) {
+        cmin = min(cmin, __shfl_xor(cmin, off));
+        cmax = max(cmax, __shfl_xor(cmax, off));
+    }
+    int nbk = 1;
+    while (nbk < NBMAX && nbk * 4 < n) nbk <<= 1;
+    // bucket(c) = ((c - cmin) * scale) >> 32 with scale = floor(2^32 nbk /
+    // range): non-decreasing in c and below nbk for c <= cmax.
+    const uint64_t range = static_cast<uint64_t>(cmax - cmin) + 1u;
+    const uint64_t scale = (static_cast<uint64_t>(nbk) << 32) / range;
+    int* cnt = bcnt[wave];
+    int* start = bstart[wave];
+    uint64_t* K = keys[wave];
+    for (int b = lane; b < nbk; b += kWave) cnt[b] = 0;
+    wave_lds_sync();
+    int bs[E];  // bucket << 16 | slot in bucket
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+        bs[u] = 0;
+        if (u < umax && lane + kWave * u < n) {
+            const uint32_t c = wd[u] >> bits;
+            const int bk = static_cast<int>((static_cast<uint64_t>(c - static_cast<uint32_t>(cmin)) * scale) >> 32);
+            bs[u] = (bk << 16) | atomicAdd(&cnt[bk], 1);
+        }
+    }
+    wave_lds_sync();
+    // Exclusive scan of the counts: lane l sums buckets [l*per, (l+1)*per).
+    const int per = (nbk + kWave - 1) / kWave;
+    int mysum = 0, mymax = 0;
+    for (int k = 0; k < per; ++k) {
+        const int b = lane * per + k;
+        if (b < nbk) {
+            mysum += cnt[b];
+            mymax = max(mymax, cnt[b]);
+        }
+    }
+    int incl = mysum;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int t = __shfl_up(incl, off);
+        if (lane >= off) incl += t;
+    }
+#pragma unroll
+    for (int off = kWave / 2; off >= 1; off >>= 1) mymax = max(mymax, __shfl_xor(mymax, off));
+    int run = incl - mysum;
+    for (int k = 0; k < per; ++k) {
+        const int b = lane * per + k;
+        if (b < nbk) {
+            start[b] = run;
+            run += cnt[b];
+        }
+    }
+    wave_lds_sync();
+    if (mymax <= kBucketMax) {
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            const int i = lane + kWave * u;
+            if (u < umax && i < n)
+                K[start[bs[u] >> 16] + (bs[u] & 0xffff)] = (static_cast<uint64_t>(wd[u]) << 32) | static_cast<uint32_t>(i);
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            const int i = lane + kWave * u;
+            if (u < umax && i < n) {
+                const int bk = bs[u] >> 16;
+                const int b0 = start[bk], b1 = b0 + cnt[bk];
+                const uint64_t key = (static_cast<uint64_t>(wd[u]) << 32) | static_cast<uint32_t>(i);
+                int pos = b0;
+                for (int k = b0; k < b1; ++k) pos += K[k] < key ? 1 : 0;
+                col_word[sr.s0 + pos] = wd[u];
+                val_out[sr.s0 + pos] = v[u];
+            }
+        }
+    } else {
+        const int P = pow2_at_least(n);
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            const int i = lane + kWave * u;
+            if (i < n)
+                K[i] = (static_cast<uint64_t>(wd[u]) << 32) | static_cast<uint32_t>(i);
+            else if (i < P)
+                K[i] = ~0ull;
+        }
+        wave_lds_sync();
+        bitonic_sort(K, P, lane, kWave, [] { wave_lds_sync(); });
+        for (int i = lane; i < n; i += kWave) {
+            const uint64_t kk = K[i];
+            col_word[sr.s0 + i] = static_cast<uint32_t>(kk >> 32);
+            val_out[sr.s0 + i] = val_in[sr.s0 + static_cast<int>(static_cast<uint32_t>(kk))];
+        }
+    }
+}
+
 // CMRS -> CSR at height 1: every strip is one row, so RowPtr is StripPtr and
 // every entry keeps its place (column = word >> bits); a plain coalesced
 // stream.  (A word with a non-zero RowInStrip is invalid input at height 1;
@@ -724,12 +894,6 @@ __global__ __launch_bounds__(kConvThreads) void sort_list_wave_kernel(
                                                      col_word, val_out, keys[wave], rtab[wave], lane);
 }
 
-// The word (col << bits | RowInStrip) of entry i of a strip.
-template <int HB>
-__device__ inline uint32_t strip_word(const StripRows& sr, const int* __restrict__ col_ind, int bits, int i) {
-    const int r = row_in_strip<HB>(sr.myrp, sr.s0 + i, 0);
-    return (static_cast<uint32_t>(col_ind[sr.s0 + i]) << bits) | static_cast<uint32_t>(r);
-}
 
 // One listed long strip of n entries by the whole 1024-thread workgroup, in K
 // (LDS, or the strip's workspace slice of 2n 64-bit words when keys_global;
@@ -795,9 +959,16 @@ __device__ __forceinline__ void sort_strip_block(const StripRows& sr, int n, int
     } else {
         const int P = pow2_at_least(n);
         sync();  // W is read above; the keys overwrite it
+        // P is a multiple of 64, so every lane of a wave takes each trip of
+        // this loop: the row lookup's cross-lane reads see all lanes.
         for (int i = tid; i < P; i += kBlockSortThreads) {
+            const int r = row_in_strip<HB>(sr.myrp, sr.s0 + i, 0);
             uint64_t key = ~0ull;
-            if (i < n) key = (static_cast<uint64_t>(strip_word<HB>(sr, col_ind, bits, i)) << 32) | static_cast<uint32_t>(i);
+            if (i < n)
+                key = (static_cast<uint64_t>((static_cast<uint32_t>(col_ind[sr.s0 + i]) << bits) |
+                                             static_cast<uint32_t>(r))
+                       << 32) |
+                      static_cast<uint32_t>(i);
             K[i] = key;
         }
         sync();
@@ -889,9 +1060,39 @@ hipError_t from_csr_g(const Conv& cv, const int* row_ptr, const int* col_ind, co
     return hipGetLastError();
 }
 
+// Tall strips: the bucket kernel (one wave per strip of up to kWaveSortCap
+// entries), then the same list kernels for longer strips.
+template <int HB, typename ET>
+hipError_t from_csr_bucket(const Conv& cv, const int* row_ptr, const int* col_ind, const void* val_in,
+                           int* strip_ptr, uint32_t* col_word, void* val_out, void* workspace, hipStream_t stream) {
+    constexpr int E = kWaveSortCap / kWave;
+    const int blocks = (cv.strips + kConvWaves - 1) / kConvWaves;
+    const auto* vin = static_cast<const ET*>(val_in);
+    auto* vout = static_cast<ET*>(val_out);
+    const FromCsrWorkspaceLayout L = from_csr_workspace_layout(cv.rows, cv.nnz, cv.height);
+    auto* ws = static_cast<char*>(workspace);
+    int* ws_count = reinterpret_cast<int*>(ws);
+    int* ws_small = reinterpret_cast<int*>(ws + L.small_off);
+    int* ws_big = reinterpret_cast<int*>(ws + L.big_off);
+    auto* gkeys = reinterpret_cast<uint64_t*>(ws + L.global_off);
+    hipLaunchKernelGGL(set_ints_kernel, dim3(1), dim3(64), 0, stream, ws_count, 2, 0);
+    hipLaunchKernelGGL((from_csr_bucket_kernel<HB, E, ET>), dim3(blocks), dim3(kConvThreads), 0, stream, cv.rows,
+                       cv.strips, cv.height, cv.bits, cv.nnz, row_ptr, col_ind, vin, strip_ptr, col_word, vout,
+                       ws_count, ws_small, ws_big);
+    const int g2 = static_cast<int>(L.big_cap < 512 ? L.big_cap : 512);
+    hipLaunchKernelGGL((sort_list_block_kernel<HB, ET>), dim3(g2), dim3(kBlockSortThreads), 0, stream, cv.rows,
+                       cv.height, cv.bits, row_ptr, col_ind, vin, col_word, vout, ws_count, ws_big, gkeys);
+    return hipGetLastError();
+}
+
 template <int HB, typename ET>
 hipError_t from_csr_hb(const Conv& cv, const int* row_ptr, const int* col_ind, const void* val_in,
                        int* strip_ptr, uint32_t* col_word, void* val_out, void* workspace, hipStream_t stream) {
+    if constexpr (HB >= kBucketMinHeight) {
+        if (static_cast<double>(cv.nnz) >= kBucketMinMean * static_cast<double>(cv.strips))
+            return from_csr_bucket<HB, ET>(cv, row_ptr, col_ind, val_in, strip_ptr, col_word, val_out, workspace,
+                                           stream);
+    }
     const ConvShape sh = conv_shape(cv.nnz, cv.strips, HB);
 #define CMRS_FROM_G(GG, EE)                                                                                      \
     if constexpr (GG >= HB) {                                                                                    \

@@ -27,138 +27,10 @@
 // XCD processes one contiguous range of strips.
 #include <mutex>
 
-#include "cmrs_device.hpp"
 #include "cmrs_internal.hpp"
+#include "spmv_device.hpp"
 
 namespace cmrs {
-
-constexpr int kSpmvWaves = 4;
-constexpr int kSpmvThreads = kSpmvWaves * kWave;
-
-template <bool NT, typename T>
-__device__ inline T stream_load(const T* p) {
-    if constexpr (NT) {
-        return __builtin_nontemporal_load(p);
-    } else {
-        return *p;
-    }
-}
-
-template <bool NT>
-__device__ inline bf16_t stream_load(const bf16_t* p) {
-    bf16_t v;
-    if constexpr (NT) {
-        v.bits = __builtin_nontemporal_load(&p->bits);
-    } else {
-        v.bits = p->bits;
-    }
-    return v;
-}
-
-// Sum, for each row r < HB, the 64 per-lane partials b[r*64 + l].  Lanes form
-// HB groups of G = 64/HB; group r sums row r: each lane adds HB consecutive
-// partials, then an xor butterfly inside the group.  Every lane of the group
-// ends with the same value.
-template <int HB, typename AT>
-__device__ inline AT reduce_rows_lds(const AT* b, int lane) {
-    constexpr int G = kWave / HB;
-    constexpr int PER = kWave / G;
-    const int r = lane / G, q = lane % G;
-    const AT* p = b + r * kWave + q * PER;
-    AT s = p[0];
-#pragma unroll
-    for (int i = 1; i < PER; ++i) s += p[i];
-#pragma unroll
-    for (int off = G / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off);
-    return s;
-}
-
-template <int HB, typename AT>
-struct LdsAcc {
-    AT* b;
-    __device__ inline void init(int lane) {
-#pragma unroll
-        for (int r = 0; r < HB; ++r) b[r * kWave + lane] = AT(0);
-    }
-    __device__ inline void add(uint32_t r, int lane, AT p) {
-        lds_add(&b[(static_cast<int>(r) & (HB - 1)) * kWave + lane], p);
-    }
-    // Row sums; lane l holds the sum of row l / (64 / HB).
-    __device__ inline AT finish(int lane) {
-        wave_lds_sync();
-        return reduce_rows_lds<HB>(b, lane);
-    }
-};
-
-template <int HB, typename AT>
-struct RegAcc {
-    AT acc[HB];
-    __device__ inline void init(int) {
-#pragma unroll
-        for (int r = 0; r < HB; ++r) acc[r] = AT(0);
-    }
-    __device__ inline void add(uint32_t r, int, AT p) {
-#pragma unroll
-        for (int k = 0; k < HB; ++k) acc[k] += (r == static_cast<uint32_t>(k)) ? p : AT(0);
-    }
-    // Reduce-scatter butterfly: at the step with xor offset o, a lane whose
-    // bit o is set keeps the upper half of its rows and sends the lower half.
-    // After log2(HB) steps lane l holds a partial of row l / (64/HB); the
-    // remaining offsets sum the group.
-    __device__ inline AT finish(int lane) {
-        int n = HB;
-#pragma unroll
-        for (int o = kWave / 2; o >= 1; o >>= 1) {
-            if (n > 1) {
-                const bool upper = (lane & o) != 0;
-#pragma unroll
-                for (int i = 0; i < HB / 2; ++i) {
-                    if (i < n / 2) {
-                        const AT send = upper ? acc[i] : acc[i + n / 2];
-                        const AT keep = upper ? acc[i + n / 2] : acc[i];
-                        acc[i] = keep + __shfl_xor(send, o);
-                    }
-                }
-                n >>= 1;
-            } else {
-                acc[0] += __shfl_xor(acc[0], o);
-            }
-        }
-        return acc[0];
-    }
-};
-
-// Entries [lo, hi) of one strip into `acc`; U batches of 64 entries have all
-// their stream loads, then all their gathers, in flight together.
-template <int U, bool NT, typename VT, typename XT, typename AT, typename Acc>
-__device__ inline void accumulate_run(Acc& acc, int lo, int hi, int bits, const uint32_t* __restrict__ word,
-                                      const VT* __restrict__ val, const XT* __restrict__ x, int lane) {
-    const uint32_t mask = (1u << bits) - 1u;
-    for (int base = lo; base < hi; base += U * kWave) {
-        // Entries past the run are clamped to its last entry (a valid
-        // address) so the stream loads of the step issue without a branch;
-        // their gathers are masked off and their products dropped.
-        uint32_t w[U];
-        VT v[U];
-        XT xv[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int j = min(base + u * kWave + lane, hi - 1);
-            w[u] = stream_load<NT>(word + j);
-            v[u] = stream_load<NT>(val + j);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (base + u * kWave + lane < hi) xv[u] = x[w[u] >> bits];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (base + u * kWave + lane < hi) {
-                const AT p = static_cast<AT>(ValTraits<VT>::widen(v[u])) * static_cast<AT>(xv[u]);
-                acc.add(w[u] & mask, lane, p);
-            }
-        }
-    }
-}
 
 // One wave per strip.  split == nullptr: the whole strip, y overwritten.
 // Otherwise run `blk` of `nb` column blocks, y overwritten for blk 0 and
@@ -202,103 +74,6 @@ __global__ __launch_bounds__(kSpmvThreads) void spmv_kernel(
             y[row] = static_cast<XT>(static_cast<AT>(y[row]) + s);
         else
             y[row] = static_cast<XT>(s);
-    }
-}
-
-// Sum each (group g, row r) set of G partials held in LDS slots
-// ((g*HB + r)*G + q, q < G) and hand the sum to out(g, r, sum).  There are
-// S = NG*HB sums: with S <= 64, L = 64/S lanes share one sum (xor butterfly);
-// otherwise every lane takes S/64 whole sums.  out() is called by a subset of
-// the lanes and must not use cross-lane operations.
-template <int HB, int G, typename AT, typename Out>
-__device__ inline void group_reduce(const AT* b, int lane, Out out) {
-    constexpr int NG = kWave / G;
-    constexpr int S = NG * HB;
-    if constexpr (S <= kWave) {
-        constexpr int L = kWave / S;
-        constexpr int PER = G / L;
-        const int si = lane / L, part = lane % L;
-        const AT* pp = b + si * G + part * PER;
-        AT s = pp[0];
-#pragma unroll
-        for (int i = 1; i < PER; ++i) s += pp[i];
-#pragma unroll
-        for (int off = L / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off);
-        if (part == 0) out(si / HB, si % HB, s);
-    } else {
-        constexpr int K = S / kWave;
-#pragma unroll
-        for (int i = 0; i < K; ++i) {
-            const int si = lane + kWave * i;
-            const AT* pp = b + si * G;
-            AT s = pp[0];
-#pragma unroll
-            for (int j = 1; j < G; ++j) s += pp[j];
-            out(si / HB, si % HB, s);
-        }
-    }
-}
-
-// Strip groups: one wave processes NG = 64/G runs at once (a run is a strip,
-// or one column block of a strip), G lanes per run.  Lane q of group g walks
-// entries lo+q, lo+q+G, ... with U stream loads and then U gathers in flight,
-// so a wave keeps 64*U entries of memory traffic outstanding instead of one
-// strip's.  Partials live in LDS slot (g*HB + r)*G + q (each lane owns its
-// slots, as in Algorithm 1).  Runs longer than long_len are skipped by their
-// group and processed afterwards by the whole wave, one at a time, with the
-// per-lane layout of spmv_kernel.  out(g, r, sum) receives every row sum.
-template <int HB, int G, int U, bool NT, typename VT, typename XT, typename AT, typename Out>
-__device__ inline void group_runs(int lo, int hi, int long_len, int bits, const uint32_t* __restrict__ word,
-                                  const VT* __restrict__ val, const XT* __restrict__ x, AT* b, int lane, Out out) {
-    const int g = lane / G, q = lane % G;
-    const bool is_long = hi - lo > long_len;
-    const uint32_t mask = (1u << bits) - 1u;
-#pragma unroll
-    for (int r = 0; r < HB; ++r) b[(g * HB + r) * G + q] = AT(0);
-    if (!is_long) {
-        for (int j0 = lo + q; j0 < hi; j0 += U * G) {
-            uint32_t w[U];
-            VT v[U];
-            XT xv[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int j = min(j0 + u * G, hi - 1);
-                w[u] = stream_load<NT>(word + j);
-                v[u] = stream_load<NT>(val + j);
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (j0 + u * G < hi) xv[u] = x[w[u] >> bits];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int j = j0 + u * G;
-                if (j < hi) {
-                    const AT p = static_cast<AT>(ValTraits<VT>::widen(v[u])) * static_cast<AT>(xv[u]);
-                    const int r = static_cast<int>(w[u] & mask) & (HB - 1);
-                    lds_add(&b[(g * HB + r) * G + q], p);
-                }
-            }
-        }
-    }
-    wave_lds_sync();
-    const uint64_t longs = ballot(is_long && q == 0);
-    group_reduce<HB, G, AT>(b, lane, [&](int gg, int rr, AT s) {
-        if (!((longs >> (gg * G)) & 1ull)) out(gg, rr, s);
-    });
-    if (longs == 0) return;
-    wave_lds_sync();
-    uint64_t rest = longs;
-    while (rest) {
-        const int leader = __ffsll(static_cast<unsigned long long>(rest)) - 1;
-        rest &= rest - 1;
-        const int llo = __shfl(lo, leader), lhi = __shfl(hi, leader);
-        LdsAcc<HB, AT> acc{b};
-        acc.init(lane);
-        accumulate_run<U, NT, VT, XT, AT>(acc, llo, lhi, bits, word, val, x, lane);
-        const AT s = acc.finish(lane);
-        constexpr int GW = kWave / HB;
-        if ((lane % GW) == 0) out(leader / G, lane / GW, s);
-        wave_lds_sync();
     }
 }
 
@@ -439,17 +214,10 @@ hipError_t launch_group_g(const Launch& L) {
     return hipGetLastError();
 }
 
-// Group width: about 8 entries per lane for the average strip, at least HB.
-inline int group_width(const cmrs_mat_t* A, int strips, int hb) {
-    const double avg = strips > 0 ? static_cast<double>(A->nnz) / strips : 0.0;
-    int g = 2;
-    while (g < 64 && g * 8 * 1.5 < avg) g <<= 1;
-    return g < hb ? hb : g;
-}
 
 template <typename VT, typename XT, typename AT, int HB, bool NT>
 hipError_t launch_group(const Launch& L) {
-    const int g = group_width(L.A, L.strips, HB);
+    const int g = spmv_group_width(L.A->nnz, L.strips, HB);
     if constexpr (HB <= 2) {
         if (g <= 2) return launch_group_g<VT, XT, AT, HB, 2, NT>(L);
     }
@@ -535,6 +303,13 @@ hipError_t dispatch(int variant, const Launch& L) {
 
 }  // namespace
 
+int spmv_group_width(int nnz, int strips, int hb) {
+    const double avg = strips > 0 ? static_cast<double>(nnz) / strips : 0.0;
+    int g = 2;
+    while (g < 64 && g * 8 * 1.5 < avg) g <<= 1;
+    return g < hb ? hb : g;
+}
+
 int resolve_spmv_variant(const cmrs_mat_t* A, int variant) {
     (void)A;
     if (variant != CMRS_SPMV_AUTO) return variant;
@@ -595,6 +370,7 @@ hipError_t launch_spmv_colblock(const cmrs_mat_t* A, const void* x, void* y, int
     if (strips == 0) return hipSuccess;
     variant = resolve_spmv_variant(A, variant);
     if (nb <= 1) return dispatch(variant, Launch{A, strips, x, y, nullptr, 1, stream});
+    if (schedule == CMRS_COLBLOCK_PHASED) return launch_spmv_phased(A, x, y, nb, split, stream);
     Launch L{A, strips, x, y, split, nb, stream};
     if (schedule == CMRS_COLBLOCK_CONCURRENT) L.partial = workspace;
     return dispatch(variant, L);

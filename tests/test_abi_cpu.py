@@ -237,3 +237,24 @@ def test_colblock_noalloc_host_checks(C):
     assert C.lib.cmrs_spmv_colblock_noalloc(ctypes.byref(small), FAKE, FAKE + 4096, 0, 0, 4, None, 0, None) == 5
     assert C.lib.cmrs_spmv_colblock_noalloc(ctypes.byref(small), FAKE, FAKE + 4096, 0, 0, 65, FAKE, 64, None) == 1
     assert C.lib.cmrs_spmv_colblock_noalloc(ctypes.byref(small), FAKE, FAKE + 8, 0, 0, 4, FAKE, 64, None) == 1
+
+
+def test_split_plan_host_checks(C):
+    d = _mat(C, rows=1000, cols=1000, nnz=5000, height=8, sorted=0)
+    n0 = C.lib.cmrs_spmv_split_plan_bytes(ctypes.byref(d), 0, 0)
+    assert n0 > 0 and n0 % 256 == 0
+    assert C.lib.cmrs_spmv_split_plan_bytes(ctypes.byref(d), -1, 0) == 0
+    assert C.lib.cmrs_spmv_split_plan_bytes(ctypes.byref(_mat(C, height=0)), 0, 0) == 0
+    p = C.SplitPlanStruct()
+    assert C.lib.cmrs_spmv_split_plan(ctypes.byref(d), 0, 0, None, 0, ctypes.byref(p), None) == 5
+    assert C.lib.cmrs_spmv_split_plan(ctypes.byref(d), 0, 0, FAKE + 4, n0, ctypes.byref(p), None) == 5  # misaligned
+    assert C.lib.cmrs_spmv_split_plan(ctypes.byref(d), 0, 0, FAKE, n0 - 1, ctypes.byref(p), None) == 5
+    assert C.lib.cmrs_spmv_split_plan(ctypes.byref(d), -2, 0, FAKE, n0, ctypes.byref(p), None) == 1
+    assert C.lib.cmrs_spmv_split_plan(ctypes.byref(d), 0, 0, FAKE, n0, None, None) == 1
+    # a plan for another shape, or with fields that do not match the matrix, is refused before any launch
+    bad = C.SplitPlanStruct(999, 5000, 8, 8, 128, 1024, 1, 1, FAKE, n0)
+    assert C.lib.cmrs_spmv_split(ctypes.byref(d), ctypes.byref(bad), FAKE + (1 << 20), FAKE + (1 << 21), 0, None) == 1
+    bad = C.SplitPlanStruct(1000, 5000, 8, 8, 0, 1024, 1, 1, FAKE, n0)
+    assert C.lib.cmrs_spmv_split(ctypes.byref(d), ctypes.byref(bad), FAKE + (1 << 20), FAKE + (1 << 21), 0, None) == 1
+    assert C.lib.cmrs_spmv_split(ctypes.byref(d), None, FAKE + (1 << 20), FAKE + (1 << 21), 0, None) == 1
+    assert C.lib.cmrs_spmv_split(ctypes.byref(d), None, FAKE + (1 << 20), FAKE + (1 << 21), 1, None) == 3

@@ -161,7 +161,7 @@ def test_long_strips_unsorted_noncanonical(C):
     for i in range(A.rows):
         a, b = A.row_ptr[i], A.row_ptr[i + 1]
         A.col_ind[a:b] = rng.permutation(A.col_ind[a:b])
-    for h in (4, 16):
+    for h in (4, 16, 32):
         M, hv = check_from_csr(C, A, h, False)
         rp2, ci2, v2 = check_round_trip(C, A, M, hv)
         assert np.array_equal(ci2.cpu().numpy(), A.col_ind)
@@ -266,3 +266,45 @@ def test_shared_long_runs(C, height, spread):
         rp2, ci2, v2 = check_round_trip(C, A, M, hv)
         assert np.array_equal(rp2.cpu().numpy(), A.row_ptr) and np.array_equal(ci2.cpu().numpy(), A.col_ind)
         assert np.array_equal(G.val_bits(v2), A.val.view(np.uint64))
+
+
+def _rows_matrix(rng, rows, cols, lengths, col_fn, canonical=True):
+    cl = []
+    for i, k in enumerate(lengths):
+        c = col_fn(i, int(k)) if k else np.zeros(0, np.int64)
+        c = np.sort(c) if canonical else c
+        cl.append(c)
+    rp = np.zeros(rows + 1, np.int64)
+    np.cumsum([c.size for c in cl], out=rp[1:])
+    col = np.concatenate(cl).astype(np.int32) if cl else np.zeros(0, np.int32)
+    return synth.Csr(rows, cols, rp.astype(np.int32), col, rng.standard_normal(col.size))
+
+
+@pytest.mark.parametrize("height", [16, 32])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_tall_strips_bucket_sort(C, height, dtype):
+    """Strips of 320..1100 entries on average (the one-wave bucket sort of
+    tall strips): uniform columns, unsorted rows with duplicate columns,
+    columns bunched in two clusters far apart (more than 64 keys in one
+    bucket: the bitonic fallback), a few strips beyond 1024 entries (the
+    workgroup list), empty strips and a ragged last strip."""
+    rng = np.random.default_rng(height)
+    rows, cols = 40 * height + 5, 1 << 22
+    mean = 1100 // height + 1
+    k = rng.poisson(mean, rows)
+    k[rng.random(rows) < 0.05] = 0
+    k[: height] = 0                      # an empty first strip
+    k[3 * height + 1] = 3000             # strips past 1024 entries
+    A = _rows_matrix(rng, rows, cols, k, lambda i, n: rng.choice(cols, size=n, replace=False))
+    check_from_csr(C, A, height, True, dtype)
+    # unsorted rows with duplicates inside a row
+    B = _rows_matrix(rng, rows, cols, k, lambda i, n: rng.integers(0, cols, n), canonical=False)
+    check_from_csr(C, B, height, True, dtype)
+    # two tight clusters at both ends of the column range
+    Cl = _rows_matrix(rng, rows, cols, k, lambda i, n: np.where(
+        rng.random(n) < 0.5, rng.integers(0, 40, n), cols - 1 - rng.integers(0, 40, n)), canonical=False)
+    check_from_csr(C, Cl, height, True, dtype)
+    # band around the diagonal plus scattered columns (the skewed workload's shape)
+    D = _rows_matrix(rng, rows, cols, k, lambda i, n: np.unique(np.concatenate(
+        [np.clip(i + rng.integers(-512, 513, max(1, 7 * n // 10)), 0, cols - 1), rng.integers(0, cols, n // 3)])))
+    check_from_csr(C, D, height, True, dtype)

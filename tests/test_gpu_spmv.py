@@ -268,18 +268,22 @@ def test_c2_full_fp32(C, c2, c2x, c2b, height):
 @pytest.mark.parametrize("height", [1, 2, 4, 8, 16, 32])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_c2_full_colblock_concurrent(C, c2, c2x, c2b, height, dtype):
-    """The concurrent column-blocked schedule with 4 and 8 blocks at every
-    height (the benchmark's and the selector's colblock classes), full size:
+    """The concurrent (4 and 8 blocks) and phased (4, 8, 16 blocks)
+    column-blocked schedules at every height (the benchmark's and the
+    selector's colblock classes), full size:
     the launcher picks its group width from the run length, so every width
     these heights reach on this matrix is exercised."""
     rp, ci, v, _ = G.upload(c2, dtype)
     M = C.from_csr(rp, ci, v, c2.cols, height, sort=True)
     xt, _ = G.xy_vector(c2x, dtype)
-    for nb in (4, 8):
+    for nb in (4, 8, 16):
         plan = C.colblock_plan(M, nb)
-        y = C.spmv_colblock(M, plan, xt, schedule="concurrent")
-        torch.cuda.synchronize()
-        c2b.check(y.cpu().numpy().astype(np.float64), dtype, f"h={height} nb={nb}")
+        for schedule in ("concurrent", "phased"):
+            if schedule == "concurrent" and nb == 16:
+                continue
+            y = C.spmv_colblock(M, plan, xt, schedule=schedule)
+            torch.cuda.synchronize()
+            c2b.check(y.cpu().numpy().astype(np.float64), dtype, f"h={height} nb={nb} {schedule}")
 
 
 @pytest.fixture(scope="module")
@@ -308,9 +312,10 @@ def test_c3_full_colblock_concurrent(C, c3, c3b, dtype):
         M = C.from_csr(rp, ci, v, c3.cols, h, sort=True)
         for nb in (4, 8):
             plan = C.colblock_plan(M, nb)
-            y = C.spmv_colblock(M, plan, xt, schedule="concurrent")
-            torch.cuda.synchronize()
-            c3b.check(y.cpu().numpy().astype(np.float64), dtype, f"h={h} nb={nb}")
+            for schedule in ("concurrent", "phased"):
+                y = C.spmv_colblock(M, plan, xt, schedule=schedule)
+                torch.cuda.synchronize()
+                c3b.check(y.cpu().numpy().astype(np.float64), dtype, f"h={h} nb={nb} {schedule}")
 
 
 def run_colblock(C, A, x64, height, nb, dtype="f64", variant="auto", schedule="passes"):
@@ -328,7 +333,8 @@ def run_colblock(C, A, x64, height, nb, dtype="f64", variant="auto", schedule="p
 def test_colblock(C, nb, height):
     A = synth.random_csr(3000, 2000, max_row=40, seed=nb + height, int_values=True)
     x = np.random.default_rng(nb).integers(-7, 8, A.cols).astype(np.float64)
-    for variant, schedule in (("lds", "passes"), ("reg", "passes"), ("group_nt", "passes"), ("auto", "concurrent")):
+    for variant, schedule in (("lds", "passes"), ("reg", "passes"), ("group_nt", "passes"), ("auto", "concurrent"),
+                              ("auto", "phased")):
         y, _, _, M, plan = run_colblock(C, A, x, height, nb, variant=variant, schedule=schedule)
         assert np.array_equal(y, oracle.csr_spmv(A.row_ptr, A.col_ind, A.val, x))
     if nb > 1:
@@ -346,7 +352,8 @@ def test_colblock(C, nb, height):
 def test_colblock_bounds_fp64_fp32(C):
     A = synth.poisson_rows(300000, 16.0, seed=5)
     x = synth.normal_vector(A.cols, seed=6)
-    for nb, schedule in ((2, "passes"), (4, "passes"), (8, "concurrent"), (3, "concurrent")):
+    for nb, schedule in ((2, "passes"), (4, "passes"), (8, "concurrent"), (3, "concurrent"), (8, "phased"),
+                         (5, "phased")):
         y, _, _, _, _ = run_colblock(C, A, x, 8, nb, schedule=schedule)
         assert_fp64_bound(A, x, y)
         y, hv, xs, _, _ = run_colblock(C, A, x, 8, nb, "f32", schedule=schedule)
@@ -371,8 +378,9 @@ def test_colblock_concurrent_long_rows_and_c2(C, c2, c2x, height):
     A = synth.Csr(3000, cols, rp.astype(np.int32), np.concatenate(cl).astype(np.int32), rng.standard_normal(int(k.sum())))
     x = synth.normal_vector(cols, seed=3)
     for nb in (2, 8):
-        y, _, _, _, _ = run_colblock(C, A, x, height, nb, schedule="concurrent")
-        assert_fp64_bound(A, x, y)
+        for schedule in ("concurrent", "phased"):
+            y, _, _, _, _ = run_colblock(C, A, x, height, nb, schedule=schedule)
+            assert_fp64_bound(A, x, y)
 
 
 def test_colblock_needs_sorted(C):
