@@ -67,7 +67,7 @@ def parse():
     p.add_argument("--rows", type=int, default=1 << 20)
     p.add_argument("--no-extras", action="store_true",
                    help="skip the selector, batched, precision and padded reports")
-    p.add_argument("--only", choices=["batched", "precision", "structured"], default=None,
+    p.add_argument("--only", choices=["batched", "precision", "structured", "residual"], default=None,
                    help="run only that report (for profiling) and print it as one JSON line")
     p.add_argument("--batched-fixed", default=None,
                    help="skip the batched autotuner: dtype=height:tile_nnz:group:blocks_per_cu[,dtype=...]")
@@ -288,32 +288,112 @@ def precision_report():
                 v = torch.from_numpy(synth.round_to_bf16_bits(A.val).view(np.int16).copy()).view(torch.bfloat16).to(dev)
             x = torch.from_numpy(synth.round_to_f32(x64)).to(dev)
             sv, sx, u, rep = (4 if dt == "f32" else 2), 4, 2.0 ** -24, (0.0 if dt == "f32" else 2.0 ** -8)
+        # (height, schedule) with the fastest cold SpMV: strip groups (the
+        # library default) or the split schedule for the long strips.
+        table = []
         best = None
-        for h in (4, 8, 16):
+        for h in (8, 16, 32):
             M = cmrs.from_csr(rp, ci, v, A.cols, h, sort=True)
-            tm = _median_ms(lambda: cmrs.spmv(M, x))
-            if best is None or tm < best[0]:
-                y = cmrs.spmv(M, x).cpu().numpy().astype(np.float64)
-                best = (tm, h, y, M.strips)
-            del M
-        tm, h, y, strips = best
-        M = cmrs.from_csr(rp, ci, v, A.cols, h, sort=True)
-        tc = _cold_ms(lambda: cmrs.spmv(M, x))
-        del M
+            plan = cmrs.split_plan(M)
+            y = torch.empty(A.rows, dtype=x.dtype, device=dev)
+            for sched, fn in (("group", lambda: cmrs.spmv(M, x, out=y)),
+                              ("split", lambda: cmrs.spmv_split(M, plan, x, out=y))):
+                tc = _cold_ms(fn)
+                table.append({"height": h, "schedule": sched, "spmv_cold_ms": round(tc, 5)})
+                if best is None or tc < best[0]:
+                    fn()
+                    best = (tc, h, sched, y.cpu().numpy().astype(np.float64), M.strips, _median_ms(fn))
+            del M, plan
+        tc, h, sched, y, strips, tm = best
         bp = model.beta_plus(A.nnz, A.rows, A.cols, strips, sv, sx, sx)
         err = np.abs(y - yref)
         # Bound of the path: fp64 4 k u |A||x|; fp32 / bf16 values with fp32 x: rounding of the stored value
         # (bf16: 2^-8) and of x (2^-24) plus fp32 accumulation.
         bound = 4 * k * u * absmv if dt == "f64" else 2.0 * (rep + (k + 2) * u) * absmv
         nz = absmv > 0
-        out[dt] = {"height": h, "spmv_warm_ms": round(tm, 5), "spmv_cold_ms": round(tc, 5),
+        out[dt] = {"height": h, "schedule": sched, "spmv_warm_ms": round(tm, 5), "spmv_cold_ms": round(tc, 5),
+                   "table": table,
                    "gbs_plus": round(bp / tc / 1e6, 1), "frac_of_hbm_peak": round(bp / tc / 1e6 / HBM_PEAK_GBS, 4),
                    "gbs_plus_warm": round(bp / tm / 1e6, 1),
                    "max_err_over_bound": float((err[nz] / bound[nz]).max()) if nz.any() else 0.0,
                    "rows_over_bound": int((err > bound).sum()),
                    "max_componentwise_rel_err": float((err[nz] / absmv[nz]).max()) if nz.any() else 0.0}
-        log(f"precision {dt}: h={h} cold {tc * 1e3:.1f} us ({bp / tc / 1e6:.0f} GB/s), warm {tm * 1e3:.1f} us, max err/bound "
+        log(f"precision {dt}: h={h} {sched} cold {tc * 1e3:.1f} us ({bp / tc / 1e6:.0f} GB/s), warm {tm * 1e3:.1f} us, max err/bound "
             f"{out[dt]['max_err_over_bound']:.3g}")
+    sink = torch.zeros(1, dtype=torch.float64, device=dev)
+    M = cmrs.from_csr(rp, ci, torch.from_numpy(A.val).to(dev), A.cols, 16, sort=True)
+    ts = _cold_ms(lambda: cmrs.calib_stream_read(M, 0, sink))
+    far = np.random.default_rng(2).integers(0, A.cols, A.nnz).astype(np.int32)
+    idx = torch.from_numpy(far).to(dev)
+    x64d = torch.from_numpy(x64).to(dev)
+    tg = _cold_ms(lambda: cmrs.calib_gather(idx, x64d, sink))
+    # The workload's own column sequence as a gather stream (its locality, no other work).
+    own = torch.from_numpy(A.col_ind).to(dev)
+    to = _cold_ms(lambda: cmrs.calib_gather(own, x64d, sink))
+    out["ceiling_f64"] = {"stream_read_gbs": round(12 * A.nnz / ts / 1e6, 1),
+                          "stream_read_ms": round(ts, 5),
+                          "random_gathers_ms": round(tg, 5), "own_column_gathers_ms": round(to, 5)}
+    log(f"precision ceilings: stream {12 * A.nnz / ts / 1e6:.0f} GB/s ({ts * 1e3:.1f} us), nnz random gathers "
+        f"{tg * 1e3:.1f} us, the matrix's own gathers {to * 1e3:.1f} us")
+    del M, idx, own
+    return out
+
+
+def residual_report():
+    """fp64 kept where a solver's stability needs it: mixed-precision
+    iterative refinement on a strictly diagonally dominant matrix with the
+    skewed workload's pattern.  Each outer step computes r = b - A x with the
+    fp64 SpMV and corrects x by three Jacobi sweeps on A d = r that use the
+    fp32 or bf16-value SpMV; the same iteration with the residual itself
+    taken by the low-precision SpMV stalls at that precision.  Errors are
+    ||x - x*||_inf / ||x*||_inf against the known solution x*."""
+    import torch
+    import scipy.sparse as sp
+    import oracle
+    import synth
+    from paper_1203_2946_amd import cmrs
+    dev = torch.device("cuda:0")
+    B = synth.zipf_clustered(2_000_000, seed=0)
+    N = sp.csr_matrix((B.val, B.col_ind, B.row_ptr), shape=(B.rows, B.cols))
+    d = 2.0 * np.asarray(abs(N).sum(axis=1)).ravel() + 1.0
+    A = (N + sp.diags(d)).tocsr()
+    A.sort_indices()
+    rp_h, ci_h, v_h = A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64)
+    xs = synth.uniform_vector(B.rows, seed=7)
+    b = oracle.csr_spmv(rp_h, ci_h, v_h, xs)
+    rp, ci = torch.from_numpy(rp_h).to(dev), torch.from_numpy(ci_h).to(dev)
+    M64 = cmrs.from_csr(rp, ci, torch.from_numpy(v_h).to(dev), B.cols, 16, sort=True)
+    Ml = {"f32": cmrs.from_csr(rp, ci, torch.from_numpy(synth.round_to_f32(v_h)).to(dev), B.cols, 16, sort=True),
+          "bf16": cmrs.from_csr(rp, ci, torch.from_numpy(synth.round_to_bf16_bits(v_h).view(np.int16).copy())
+                                .view(torch.bfloat16).to(dev), B.cols, 16, sort=True)}
+    b64 = torch.from_numpy(b).to(dev)
+    dinv = torch.from_numpy(1.0 / d).to(dev)
+    xs_t = torch.from_numpy(xs).to(dev)
+    nx = float(np.abs(xs).max())
+    out = {"matrix": f"skewed-row pattern (n={B.rows}) plus diagonal 2 sum|a_ij| + 1, x* U[-1,1] seed 7, b = A x* "
+                     f"(oracle, fp64)", "outer": 20, "inner_jacobi_sweeps": 3}
+
+    def err(x):
+        return float((x.double() - xs_t).abs().max().item()) / nx
+
+    for low, ML in Ml.items():
+        for resid in ("f64", low):
+            x = torch.zeros(B.rows, dtype=torch.float64, device=dev)
+            hist = []
+            for _ in range(20):
+                if resid == "f64":
+                    r = b64 - cmrs.spmv(M64, x)
+                else:
+                    r = (b64.float() - cmrs.spmv(ML, x.float())).double()
+                r32, dd = r.float(), torch.zeros(B.rows, dtype=torch.float32, device=dev)
+                dinv32 = dinv.float()
+                for _ in range(3):
+                    dd = dd + dinv32 * (r32 - cmrs.spmv(ML, dd))
+                x = x + dd.double()
+                hist.append(err(x))
+            out[f"{low}_inner_{resid}_residual"] = {"final_rel_err": hist[-1],
+                                                    "rel_err_every_5": [hist[i] for i in (4, 9, 14, 19)]}
+            log(f"refinement: {low} inner, {resid} residual: rel err {hist[-1]:.3g}")
     return out
 
 
@@ -467,9 +547,14 @@ def compact_line(res: dict) -> str:
                             "regret_default": s["fresh"]["regret_default_h8_group"]}
     if "precision" in ex:
         p = ex["precision"]
-        summ["precision_zipf"] = {dt: pick(p[dt], ("height", "spmv_cold_ms", "gbs_plus", "frac_of_hbm_peak",
-                                                   "max_err_over_bound", "rows_over_bound"))
+        summ["precision_zipf"] = {dt: pick(p[dt], ("height", "schedule", "spmv_cold_ms", "gbs_plus",
+                                                   "frac_of_hbm_peak", "max_err_over_bound", "rows_over_bound"))
                                   for dt in ("f64", "f32", "bf16") if dt in p}
+        if "ceiling_f64" in p:
+            summ["precision_zipf"]["ceiling_f64"] = p["ceiling_f64"]
+    if "residual" in ex:
+        r = ex["residual"]
+        summ["residual_refinement"] = {k: r[k]["final_rel_err"] for k in r if k.endswith("_residual")}
     if "batched" in ex:
         b = ex["batched"]
         summ["batched"] = {dt: pick(b[dt], ("graph_persistent_ms", "separate_launches_ms", "speedup_vs_separate",
@@ -522,8 +607,8 @@ def main():
         print(json.dumps({"copy_calibration_bytes": a.numel() * 4, "copies": 3}), flush=True)
         return
     if args.only:
-        rep = (batched_report(args.batched_fixed) if args.only == "batched"
-               else precision_report() if args.only == "precision" else structured_report())
+        rep = {"batched": lambda: batched_report(args.batched_fixed), "precision": precision_report,
+               "structured": structured_report, "residual": residual_report}[args.only]()
         print(json.dumps({args.only: rep}), flush=True)
         return
     dev = torch.device("cuda:0")
@@ -712,7 +797,7 @@ def main():
 
     # Achievable ceilings: read-only pass over the streams (Sec. 6.3) and the random-gather rate into x.
     sink = torch.zeros(1, dtype=torch.float64, device=dev)
-    ts, _ = protocol(lambda: cmrs.calib_stream_read(P64.M, P64.h, sink), cold=True)
+    ts, _ = protocol(lambda: cmrs.calib_stream_read(P64.M, 0, sink), cold=True)
     stream_bytes = 12 * A.nnz
     idx = torch.from_numpy(np.random.default_rng(2).integers(0, A.cols, A.nnz).astype(np.int32)).to(dev)
     tg, _ = protocol(lambda: cmrs.calib_gather(idx, P64.x, sink), cold=True)
@@ -738,6 +823,7 @@ def main():
         extras["padded"] = padded_report(rp, ci, v64, x_d["f64"], A.cols, A.nnz, best_plain)
         extras["selector"] = selector_report(rp, ci, v64, A.cols)
         extras["precision"] = precision_report()
+        extras["residual"] = residual_report()
         extras["structured"] = structured_report()
         extras["batched"] = batched_report()
 

@@ -18,9 +18,13 @@ def _canned():
         "selector": {"this_workload": {"tune_ratio": 1.0, "predicted": "h32_colblock4", "exhaustive_best": "h32_colblock4"},
                      "fresh": {"regret": 0.0098, "regret_default_h8_group": 0.08},
                      "held_out": {"regret": 0.0243}},
-        "precision": {dt: {"height": 16, "spmv_cold_ms": 0.1394, "gbs_plus": 1356.2, "frac_of_hbm_peak": 0.1695,
+        "precision": {**{dt: {"height": 16, "schedule": "split", "spmv_cold_ms": 0.1394, "gbs_plus": 1356.2, "frac_of_hbm_peak": 0.1695,
                            "max_err_over_bound": 0.238, "rows_over_bound": 0, "extra": list(range(50))}
-                      for dt in ("f64", "f32", "bf16")},
+                         for dt in ("f64", "f32", "bf16")},
+                      "ceiling_f64": {"stream_read_gbs": 6012.3, "stream_read_ms": 0.02601, "random_gathers_ms": 0.1234,
+                                      "own_column_gathers_ms": 0.0712}},
+        "residual": {f"{low}_inner_{r}_residual": {"final_rel_err": 1.234e-16, "rel_err_every_5": [1e-3] * 4}
+                     for low in ("f32", "bf16") for r in ("f64", low)},
         "batched": {dt: {"graph_persistent_ms": 6.896, "separate_launches_ms": 7.505, "speedup_vs_separate": 1.088,
                          "frac_of_hbm_peak": 0.2825, "tuning": {"tile_nnz": 32768}} for dt in ("f64", "f32")},
         "structured": {k: {"f64": {"eta_plus": 0.57}, "f32": {"eta_plus": 0.7}} for k in ("stencil27", "band_bw40")},
@@ -66,7 +70,8 @@ def test_line_is_short_and_complete():
     assert set(d["roofline"]) >= {"bound", "achieved", "peak", "unit", "frac", "traffic"}
     assert set(d["cpu_baseline"]) >= {"value", "unit", "cores", "kind", "sample"}
     assert d["roofline"]["frac"] == round(d["roofline"]["achieved"] / d["roofline"]["peak"], 4)
-    assert set(d["reports"]) == {"selector", "precision_zipf", "batched", "structured", "padded", "model_eq52"}
+    assert set(d["reports"]) == {"selector", "precision_zipf", "batched", "structured", "padded", "model_eq52",
+                                 "residual_refinement"}
     assert "extras" not in d and "sweep" not in d
 
 
