@@ -82,16 +82,18 @@ __device__ inline void spmm_pass(const SpmmMat& m, int sb, int s_end, AT* __rest
                 w[u] = nt_load(m.word + j);
                 v[u] = nt_load(val + j);
             }
-            // The row piece x[col][0 .. nrhs) of every entry.  fp32 X: 16-byte
-            // loads where X keeps its rows aligned, single loads otherwise, the
-            // slots past nrhs not loaded (nrhs is the same in every lane).  fp64
-            // X: one load per slot (measured faster for fp64 than the paired
-            // loads: 7.25 against 8.48 ms on the uneven batch).
+            // The row piece x[col][0 .. nrhs) of every entry: 16-byte loads
+            // where X keeps its rows aligned, single loads otherwise, the slots
+            // past nrhs not loaded (nrhs is the same in every lane).  fp64 X
+            // with fewer than 4 right-hand-side slots: one load per slot, the
+            // slots past nrhs reading x_0 (measured faster there; from 4 slots
+            // on the 16-byte loads are faster, e.g. 481 -> 363 us for 8
+            // right-hand sides on a 27-point stencil of 2*10^6 rows).
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (base + u * G < hi) {
                     const XT* xr = x + static_cast<size_t>(w[u] >> bits) * ldx;
-                    if constexpr (sizeof(XT) == 8) {
+                    if constexpr (sizeof(XT) == 8 && RB < 4) {
 #pragma unroll
                         for (int k = 0; k < RB; ++k) xv[u][k] = xr[k < nrhs ? k : 0];
                     } else if (RB >= XV && m.xvec) {
