@@ -67,7 +67,8 @@ def parse():
     p.add_argument("--rows", type=int, default=1 << 20)
     p.add_argument("--no-extras", action="store_true",
                    help="skip the selector, batched, precision and padded reports")
-    p.add_argument("--only", choices=["batched", "precision", "structured", "residual"], default=None,
+    p.add_argument("--only", choices=["batched", "precision", "structured", "residual", "padded_small_mu"],
+                   default=None,
                    help="run only that report (for profiling) and print it as one JSON line")
     p.add_argument("--batched-fixed", default=None,
                    help="skip the batched autotuner: dtype=height:tile_nnz:group:blocks_per_cu[,dtype=...]")
@@ -530,6 +531,17 @@ def model_vs_sweep(sweep, mu):
     return out
 
 
+def _round_floats(o, sig: int = 4):
+    """Floats rounded to `sig` significant digits, recursively."""
+    if isinstance(o, float):
+        return float(f"{o:.{sig}g}")
+    if isinstance(o, dict):
+        return {k: _round_floats(v, sig) for k, v in o.items()}
+    if isinstance(o, (list, tuple)):
+        return [_round_floats(v, sig) for v in o]
+    return o
+
+
 def compact_line(res: dict) -> str:
     """The one stdout JSON line: the headline, the roofline, the CPU baseline
     and one-line summaries of every report (the full tables go to the detail
@@ -564,9 +576,12 @@ def compact_line(res: dict) -> str:
                               for k, v in ex["structured"].items()}
     if "padded" in ex:
         summ["padded"] = {k: pick(v, ("memory_overhead", "speedup_vs_best_plain")) for k, v in ex["padded"].items()}
+    if "padded_small_mu" in ex:
+        summ["padded_small_mu"] = {k: [v["mu"], v["padded_h8"]["speedup_vs_best_plain"],
+                                       v["padded_h16"]["speedup_vs_best_plain"]] for k, v in ex["padded_small_mu"].items()}
     if "model" in ex:
-        summ["model_eq52"] = [[r["dtype"], r["height"], r["a_lambda128_b4"], r["measured_wave"], r["measured_best"]]
-                              for r in ex["model"]["rows"]]
+        summ["model_eq52_f64"] = [[r["height"], r["a_lambda128_b4"], r["measured_wave"], r["measured_best"]]
+                                  for r in ex["model"]["rows"] if r["dtype"] == "f64"]
     line = {k: res[k] for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
                                  "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config",
                                  "roofline", "cpu_baseline") if k in res}
@@ -574,13 +589,58 @@ def compact_line(res: dict) -> str:
         if k in res:
             line[k] = res[k]
     if summ:
-        line["reports"] = summ
+        line["reports"] = _round_floats(summ)
     if "detail_file" in res:
         line["detail_file"] = res["detail_file"]
     txt = json.dumps(line, separators=(",", ":"))
     if len(txt) > 4000:
         raise ValueError(f"bench line is {len(txt)} characters (limit 4000)")
     return txt
+
+
+def padded_small_mu_report():
+    """The padded layout of Sec. 6.7 where the paper reports its gains, small
+    mean row lengths: a random permutation (mu = 1), Poisson(2) and Poisson(4)
+    row lengths with uniform columns, and the 5-point Laplacian of a 1024^2
+    grid (mu ~ 5), n ~ 2^20, fp64.  Best plain SpMV over heights 1..32 and
+    the two main schedules against the padded SpMV at heights 8 and 16, cold
+    (paper protocol)."""
+    import torch
+    import synth
+    from paper_1203_2946_amd import cmrs
+    dev = torch.device("cuda:0")
+    out = {}
+    mats = (("permutation", lambda: synth.permutation(1 << 20, seed=3)),
+            ("poisson2", lambda: synth.poisson_rows(1 << 20, 2.0, seed=3)),
+            ("poisson4", lambda: synth.poisson_rows(1 << 20, 4.0, seed=3)),
+            ("laplace2d_1024", lambda: synth.laplace2d(1024)))
+    for name, make in mats:
+        A = make()
+        rp, ci = torch.from_numpy(A.row_ptr).to(dev), torch.from_numpy(A.col_ind).to(dev)
+        v = torch.from_numpy(A.val).to(dev)
+        x = torch.from_numpy(synth.normal_vector(A.cols, seed=4)).to(dev)
+        y = torch.empty(A.rows, dtype=torch.float64, device=dev)
+        best = None
+        for h in (1, 2, 4, 8, 16, 32):
+            M = cmrs.from_csr(rp, ci, v, A.cols, h, sort=True)
+            for var in ("auto", "lds_nt"):
+                t = _cold_ms(lambda: cmrs.spmv(M, x, out=y, variant=var))
+                if best is None or t < best[0]:
+                    best = (t, h, var)
+            del M
+        res = {"mu": round(A.nnz / A.rows, 3), "best_plain": {"height": best[1], "variant": best[2],
+                                                              "cold_ms": round(best[0], 5)}}
+        for h in (8, 16):
+            P = cmrs.padded_from_csr(rp, ci, v, A.cols, h)
+            t = _cold_ms(lambda: cmrs.padded_spmv(P, x, out=y))
+            res[f"padded_h{h}"] = {"cold_ms": round(t, 5), "memory_overhead": round(P.nnz / A.nnz - 1, 4),
+                                   "speedup_vs_best_plain": round(best[0] / t, 3)}
+            del P
+        out[name] = res
+        log(f"padded small mu {name}: plain h={best[1]} {best[2]} {best[0] * 1e3:.1f} us; padded h8 "
+            f"{res['padded_h8']['cold_ms'] * 1e3:.1f} us, h16 {res['padded_h16']['cold_ms'] * 1e3:.1f} us")
+        del rp, ci, v, x, y
+    return out
 
 
 def main():
@@ -608,7 +668,8 @@ def main():
         return
     if args.only:
         rep = {"batched": lambda: batched_report(args.batched_fixed), "precision": precision_report,
-               "structured": structured_report, "residual": residual_report}[args.only]()
+               "structured": structured_report, "residual": residual_report,
+               "padded_small_mu": padded_small_mu_report}[args.only]()
         print(json.dumps({args.only: rep}), flush=True)
         return
     dev = torch.device("cuda:0")
@@ -821,6 +882,7 @@ def main():
         del P64
         torch.cuda.empty_cache()
         extras["padded"] = padded_report(rp, ci, v64, x_d["f64"], A.cols, A.nnz, best_plain)
+        extras["padded_small_mu"] = padded_small_mu_report()
         extras["selector"] = selector_report(rp, ci, v64, A.cols)
         extras["precision"] = precision_report()
         extras["residual"] = residual_report()

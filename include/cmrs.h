@@ -418,7 +418,13 @@ cmrs_status_t cmrs_spmm_batched(const cmrs_spmm_plan_t *plan, hipStream_t stream
  * cmrs_padded_spmv: y = A x for a padded matrix: A->strip_ptr from the plan,
  *   A->nnz = padded_nnz, A->bits = cmrs_padded_bits(height), A->sorted
  *   ignored.  Every row of y is written (empty rows +0); error bound and
- *   dtypes as for cmrs_spmv.
+ *   dtypes as for cmrs_spmv.  Precondition: the entries are arranged as
+ *   cmrs_padded_from_csr arranges them (at most 8 entries of a row in any
+ *   64-entry chunk, the constraint of Sec. 6.7).  Lanes l, l+8, ... of a
+ *   chunk share copy l mod 8 of the row sums; with fp32 or bf16 values that
+ *   copy is updated by a plain read-modify-write, so an arrangement that
+ *   breaks the constraint gives unspecified fp32/bf16 results (fp64 uses
+ *   the LDS atomic add and stays correct).
  */
 int32_t cmrs_padded_bits(int32_t height);
 size_t cmrs_padded_plan_workspace(int32_t rows, int32_t height);

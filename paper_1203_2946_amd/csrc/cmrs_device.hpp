@@ -49,11 +49,14 @@ __device__ inline uint64_t lanemask_lt() {
     return l == 0 ? 0ull : (~0ull >> (64 - l));
 }
 
-// Add v to an LDS partial sum that only the calling lane updates (until the
-// wave synchronises).  fp64 uses the LDS atomic add, one instruction.  The
-// fp32 LDS atomic add runs about 25x below the LDS rate on gfx950 (measured
-// with lane-private slots), so fp32 partials take a plain read-modify-write,
-// which is exact and safe for a lane-owned slot.
+// Add v to an LDS partial sum that no other lane of the same instruction
+// updates: a lane-owned slot, or (the padded kernel of Sec. 6.7) a copy
+// shared by lanes that the padded arrangement keeps from ever holding
+// entries of the same row in one 64-entry chunk.  fp64 uses the LDS atomic
+// add, one instruction.  The fp32 LDS atomic add runs about 25x below the
+// LDS rate on gfx950 (measured with lane-private slots), so fp32 partials
+// take a plain read-modify-write, which is exact under that condition and
+// would lose additions without it.
 template <typename AT>
 __device__ inline void lds_add(AT* p, AT v) {
     *p += v;

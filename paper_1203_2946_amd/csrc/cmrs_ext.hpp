@@ -72,7 +72,7 @@ struct SplitChunk {
 constexpr int kSplitU = 8;  // entries per lane in flight (stream loads, then gathers)
 struct SplitShape {
     int group, long_len, chunk_len, max_heavy, max_chunks;
-    size_t heavy_off, chunk_off, partial_off, total;
+    size_t block_off, heavy_off, chunk_off, partial_off, total;
 };
 SplitShape split_shape(const cmrs_mat_t* A, int long_len, int chunk_len);
 hipError_t launch_split_plan(const cmrs_mat_t* A, const SplitShape& s, void* buf, hipStream_t stream);

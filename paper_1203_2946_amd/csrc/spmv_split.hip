@@ -30,37 +30,119 @@ namespace cmrs {
 // chunk list (the number of chunks is known on the device only).
 constexpr int kSplitChunkBlocksMax = 1024;
 
-__global__ void split_clear_kernel(int* counts) {
-    if (threadIdx.x < 4) counts[threadIdx.x] = 0;
+// The plan, in three launches and in strip order: (1) every block of 256
+// strips counts its heavy strips and their chunks; (2) one workgroup turns
+// the block counts into offsets (exclusive scan) and writes the totals;
+// (3) every block scans its strips again and writes its heavy strips and
+// their chunks at those offsets.  A heavy strip has more than long_len
+// entries and n = ceil(len / chunk_len) chunks of len / n entries (one more
+// for the first len % n).  No atomics, so the lists come out the same on
+// every build.
+constexpr int kPlanThreads = 256;
+
+struct SplitCount {
+    int heavy, chunks;
+};
+
+__device__ inline SplitCount split_strip_count(int s, int strips, int long_len, int chunk_len,
+                                               const int* __restrict__ strip_ptr, int& lo, int& len) {
+    lo = 0;
+    len = 0;
+    if (s < strips) {
+        lo = strip_ptr[s];
+        len = strip_ptr[s + 1] - lo;
+    }
+    if (s >= strips || len <= long_len) return SplitCount{0, 0};
+    return SplitCount{1, (len + chunk_len - 1) / chunk_len};
 }
 
-// One thread per strip: a strip of more than long_len entries gets a slot in
-// the heavy list and n = ceil(len / chunk_len) consecutive chunk slots, both
-// taken from counters (the list order varies from build to build; each
-// strip's chunks are contiguous and in entry order, which is all the SpMV
-// relies on).
-__global__ __launch_bounds__(256) void split_plan_kernel(int strips, int long_len, int chunk_len,
-                                                         const int* __restrict__ strip_ptr, int* __restrict__ counts,
-                                                         SplitHeavy* __restrict__ heavy, SplitChunk* __restrict__ chunks,
-                                                         int max_heavy, int max_chunks) {
-    const int stride = static_cast<int>(gridDim.x * blockDim.x);
-    for (int s = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x); s < strips; s += stride) {
-        const int lo = strip_ptr[s], hi = strip_ptr[s + 1];
-        const int len = hi - lo;
-        if (len <= long_len) continue;
-        const int n = (len + chunk_len - 1) / chunk_len;
-        const int h = atomicAdd(&counts[0], 1);
-        const int c0 = atomicAdd(&counts[1], n);
-        if (h >= max_heavy || c0 > max_chunks - n) {
-            atomicOr(&counts[2], 1);  // cannot happen within the sizes of split_shape(); reported by the plan
-            continue;
+// Exclusive scan of v over the block's 256 threads (4 waves); returns the
+// block total through *total.
+__device__ inline int block_exclusive_scan(int v, int* wave_tot, int* total) {
+    const int lane = lane_id();
+    const int wave = static_cast<int>(threadIdx.x) / kWave;
+    int inc = v;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int t = __shfl_up(inc, off);
+        if (lane >= off) inc += t;
+    }
+    if (lane == kWave - 1) wave_tot[wave] = inc;
+    __syncthreads();
+    int before = 0, all = 0;
+    for (int w = 0; w < kPlanThreads / kWave; ++w) {
+        if (w < wave) before += wave_tot[w];
+        all += wave_tot[w];
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - v;
+}
+
+__global__ __launch_bounds__(kPlanThreads) void split_count_kernel(int strips, int long_len, int chunk_len,
+                                                                   const int* __restrict__ strip_ptr,
+                                                                   int* __restrict__ block_sums) {
+    __shared__ int tot[2][kPlanThreads / kWave];
+    const int s = static_cast<int>(blockIdx.x) * kPlanThreads + static_cast<int>(threadIdx.x);
+    int lo, len;
+    const SplitCount c = split_strip_count(s, strips, long_len, chunk_len, strip_ptr, lo, len);
+    int th, tc;
+    block_exclusive_scan(c.heavy, tot[0], &th);
+    block_exclusive_scan(c.chunks, tot[1], &tc);
+    if (threadIdx.x == 0) {
+        block_sums[2 * blockIdx.x] = th;
+        block_sums[2 * blockIdx.x + 1] = tc;
+    }
+}
+
+// One workgroup: block_sums[2b], [2b+1] become the block's first heavy slot
+// and first chunk slot; counts[0], counts[1] the totals.
+__global__ __launch_bounds__(kPlanThreads) void split_scan_kernel(int nblocks, int* __restrict__ block_sums,
+                                                                  int* __restrict__ counts) {
+    __shared__ int tot[2][kPlanThreads / kWave];
+    int carry_h = 0, carry_c = 0;
+    for (int base = 0; base < nblocks; base += kPlanThreads) {
+        const int b = base + static_cast<int>(threadIdx.x);
+        const int h = b < nblocks ? block_sums[2 * b] : 0;
+        const int c = b < nblocks ? block_sums[2 * b + 1] : 0;
+        int th, tc;
+        const int oh = block_exclusive_scan(h, tot[0], &th);
+        const int oc = block_exclusive_scan(c, tot[1], &tc);
+        if (b < nblocks) {
+            block_sums[2 * b] = carry_h + oh;
+            block_sums[2 * b + 1] = carry_c + oc;
         }
-        heavy[h] = SplitHeavy{s, c0, n, 0};
-        for (int k = 0; k < n; ++k) {
-            const int a = lo + static_cast<int>(static_cast<long long>(len) * k / n);
-            const int b = lo + static_cast<int>(static_cast<long long>(len) * (k + 1) / n);
-            chunks[c0 + k] = SplitChunk{h, a, b, 0};
-        }
+        carry_h += th;
+        carry_c += tc;
+    }
+    if (threadIdx.x == 0) {
+        counts[0] = carry_h;
+        counts[1] = carry_c;
+    }
+}
+
+__global__ __launch_bounds__(kPlanThreads) void split_fill_kernel(int strips, int long_len, int chunk_len,
+                                                                  const int* __restrict__ strip_ptr,
+                                                                  const int* __restrict__ block_sums,
+                                                                  SplitHeavy* __restrict__ heavy,
+                                                                  SplitChunk* __restrict__ chunks, int max_heavy,
+                                                                  int max_chunks) {
+    __shared__ int tot[2][kPlanThreads / kWave];
+    const int s = static_cast<int>(blockIdx.x) * kPlanThreads + static_cast<int>(threadIdx.x);
+    int lo, len;
+    const SplitCount c = split_strip_count(s, strips, long_len, chunk_len, strip_ptr, lo, len);
+    int th, tc;
+    const int h = block_sums[2 * blockIdx.x] + block_exclusive_scan(c.heavy, tot[0], &th);
+    const int c0 = block_sums[2 * blockIdx.x + 1] + block_exclusive_scan(c.chunks, tot[1], &tc);
+    if (!c.heavy || h >= max_heavy || c0 > max_chunks - c.chunks) return;
+    const int n = c.chunks;
+    heavy[h] = SplitHeavy{s, c0, n, 0};
+    const int q = len / n, rem = len - q * n;
+    int a = lo;
+    for (int k = 0; k < n; ++k) {
+        const int e = a + q + (k < rem ? 1 : 0);
+        chunks[c0 + k] = SplitChunk{h, a, e, 0};
+        a = e;
     }
 }
 
@@ -147,7 +229,9 @@ SplitShape split_shape(const cmrs_mat_t* A, int long_len, int chunk_len) {
     s.max_heavy = static_cast<int>(std::min<long long>(strips, nnz / (static_cast<long long>(s.long_len) + 1)));
     s.max_chunks = static_cast<int>(std::min<long long>(nnz, nnz / s.chunk_len + s.max_heavy));
     auto up = [](size_t v) { return (v + 255) & ~static_cast<size_t>(255); };
-    s.heavy_off = 256;
+    const int nblocks = (strips + kPlanThreads - 1) / kPlanThreads;
+    s.block_off = 256;
+    s.heavy_off = up(s.block_off + 2 * sizeof(int) * static_cast<size_t>(nblocks));
     s.chunk_off = up(s.heavy_off + sizeof(SplitHeavy) * static_cast<size_t>(s.max_heavy));
     s.partial_off = up(s.chunk_off + sizeof(SplitChunk) * static_cast<size_t>(s.max_chunks));
     s.total = up(s.partial_off + sizeof(double) * static_cast<size_t>(hb) * static_cast<size_t>(s.max_chunks));
@@ -157,14 +241,17 @@ SplitShape split_shape(const cmrs_mat_t* A, int long_len, int chunk_len) {
 hipError_t launch_split_plan(const cmrs_mat_t* A, const SplitShape& s, void* buf, hipStream_t stream) {
     char* base = static_cast<char*>(buf);
     int* counts = reinterpret_cast<int*>(base);
-    hipLaunchKernelGGL(split_clear_kernel, dim3(1), dim3(64), 0, stream, counts);
     const int strips = (A->rows + A->height - 1) / A->height;
-    if (strips > 0 && s.max_heavy > 0) {
-        const int blocks = std::min((strips + 255) / 256, 4096);
-        hipLaunchKernelGGL(split_plan_kernel, dim3(blocks), dim3(256), 0, stream, strips, s.long_len, s.chunk_len,
-                           A->strip_ptr, counts, reinterpret_cast<SplitHeavy*>(base + s.heavy_off),
+    const int nblocks = (strips + kPlanThreads - 1) / kPlanThreads;
+    int* block_sums = reinterpret_cast<int*>(base + s.block_off);
+    if (nblocks > 0)
+        hipLaunchKernelGGL(split_count_kernel, dim3(nblocks), dim3(kPlanThreads), 0, stream, strips, s.long_len,
+                           s.chunk_len, A->strip_ptr, block_sums);
+    hipLaunchKernelGGL(split_scan_kernel, dim3(1), dim3(kPlanThreads), 0, stream, nblocks, block_sums, counts);
+    if (nblocks > 0 && s.max_heavy > 0)
+        hipLaunchKernelGGL(split_fill_kernel, dim3(nblocks), dim3(kPlanThreads), 0, stream, strips, s.long_len,
+                           s.chunk_len, A->strip_ptr, block_sums, reinterpret_cast<SplitHeavy*>(base + s.heavy_off),
                            reinterpret_cast<SplitChunk*>(base + s.chunk_off), s.max_heavy, s.max_chunks);
-    }
     return hipGetLastError();
 }
 

@@ -29,6 +29,10 @@ def _canned():
                          "frac_of_hbm_peak": 0.2825, "tuning": {"tile_nnz": 32768}} for dt in ("f64", "f32")},
         "structured": {k: {"f64": {"eta_plus": 0.57}, "f32": {"eta_plus": 0.7}} for k in ("stencil27", "band_bw40")},
         "padded": {f"h{h}": {"memory_overhead": 0.123, "speedup_vs_best_plain": 0.8, "padded_nnz": 1} for h in (8, 16, 32)},
+        "padded_small_mu": {k: {"mu": 1.0, "best_plain": {"height": 8, "variant": "auto", "cold_ms": 0.05},
+                                "padded_h8": {"cold_ms": 0.06, "memory_overhead": 2.1, "speedup_vs_best_plain": 0.8},
+                                "padded_h16": {"cold_ms": 0.06, "memory_overhead": 3.1, "speedup_vs_best_plain": 0.7}}
+                            for k in ("permutation", "poisson2", "poisson4", "laplace2d_1024")},
         "model": {"mu": 16.0, "rows": [{"dtype": dt, "height": h, "a_lambda128_b4": 1.5, "a_lambda64_b4": 1.2,
                                         "a_lambda128_bval": 1.3, "measured_wave": 1.4, "measured_best": 1.6}
                                        for dt in ("f64", "f32") for h in (1, 2, 4, 8, 16, 32)]},
@@ -70,8 +74,8 @@ def test_line_is_short_and_complete():
     assert set(d["roofline"]) >= {"bound", "achieved", "peak", "unit", "frac", "traffic"}
     assert set(d["cpu_baseline"]) >= {"value", "unit", "cores", "kind", "sample"}
     assert d["roofline"]["frac"] == round(d["roofline"]["achieved"] / d["roofline"]["peak"], 4)
-    assert set(d["reports"]) == {"selector", "precision_zipf", "batched", "structured", "padded", "model_eq52",
-                                 "residual_refinement"}
+    assert set(d["reports"]) == {"selector", "precision_zipf", "batched", "structured", "padded", "model_eq52_f64",
+                                 "residual_refinement", "padded_small_mu"}
     assert "extras" not in d and "sweep" not in d
 
 
