@@ -170,16 +170,6 @@ __device__ inline void group_reduce(const AT* b, int lane, Out out) {
     }
 }
 
-// Strip groups: one wave processes NG = 64/G runs at once (a run is a strip,
-// or one column block of a strip), G lanes per run.  Lane q of group g walks
-// entries lo+q, lo+q+G, ... with U stream loads and then U gathers in flight,
-// so a wave keeps 64*U entries of memory traffic outstanding instead of one
-// strip's.  Partials live in LDS slot (g*HB + r)*G + q (each lane owns its
-// slots, as in Algorithm 1).  Runs longer than long_len are skipped by their
-// group and processed afterwards by the whole wave, one at a time, with the
-// per-lane layout of spmv_kernel; with SKIP_LONG they are left alone (another
-// wave processes them) and get no out() call.  out(g, r, sum) receives every
-// other row sum.
 // Lane q of group g adds the products of entries lo+q, lo+q+G, ... < hi into
 // its LDS slots (g*HB + r)*G + q: U stream loads, then U gathers in flight.
 template <int HB, int G, int U, bool NT, typename VT, typename XT, typename AT>
@@ -211,6 +201,15 @@ __device__ inline void group_walk(int lo, int hi, int bits, const uint32_t* __re
     }
 }
 
+// Strip groups: one wave processes NG = 64/G runs at once (a run is a strip,
+// or one column block of a strip), G lanes per run, so a wave keeps 64*U
+// entries of memory traffic outstanding instead of one strip's.  Partials
+// live in LDS slot (g*HB + r)*G + q (each lane owns its slots, as in
+// Algorithm 1).  Runs longer than long_len are skipped by their group and
+// processed afterwards by the whole wave, one at a time, with the per-lane
+// layout of spmv_kernel; with SKIP_LONG they are left alone (another wave
+// processes them) and get no out() call.  out(g, r, sum) receives every other
+// row sum.
 template <int HB, int G, int U, bool NT, typename VT, typename XT, typename AT, typename Out, bool SKIP_LONG = false>
 __device__ inline void group_runs(int lo, int hi, int long_len, int bits, const uint32_t* __restrict__ word,
                                   const VT* __restrict__ val, const XT* __restrict__ x, AT* b, int lane, Out out) {
