@@ -29,9 +29,12 @@
 // (binary search) and moves to its place in the merged run.  Keys are
 // (word << 32 | position in strip), unique, so the result is the stable order.
 // Strips that are longer than a group holds, or whose rows are not sorted,
-// go to a list in the workspace and are sorted by a bitonic network: in one
-// wave's LDS (up to 1024 entries), in a 1024-thread workgroup's LDS (up to
-// 16384), or in the workspace beyond that.
+// go to a list in the workspace: strips of up to 1024 entries are sorted by
+// one wave (run merge, or a bitonic network for unsorted rows); longer ones
+// by a 1024-thread workgroup, in LDS up to 16384 entries (each entry ranked
+// against the strip's short rows gathered and sorted once, and by a binary
+// search over each long row; a bitonic network for unsorted rows), in the
+// workspace beyond that.
 #include <limits.h>
 
 #include "cmrs_device.hpp"
@@ -42,6 +45,8 @@ namespace cmrs {
 constexpr int kConvWaves = 4;
 constexpr int kConvThreads = kConvWaves * kWave;
 constexpr int kBlockSortThreads = 1024;
+// Workgroups of the long-strip sort: its LDS allows one per CU, 256 CUs.
+constexpr int kBlockSortGrid = 256;
 
 __global__ void set_ints_kernel(int32_t* p, int32_t n, int32_t v) {
     if (blockIdx.x == 0 && static_cast<int>(threadIdx.x) < n) p[threadIdx.x] = v;
@@ -981,31 +986,308 @@ __device__ __forceinline__ void sort_strip_block(const StripRows& sr, int n, int
     }
 }
 
-// Sorted conversion of the listed long strips: one 1024-thread workgroup per
-// strip, strips taken in a grid-stride loop; the keys in LDS when the strip
-// fits (n <= kBlockSortCap), else in the strip's own slice of the workspace
-// [2*s0, 2*s1).
+// Entries [lo, lo + len) of a sorted LDS array below w, for C entries at
+// once: the searches step together (binary lifting, as many steps as the
+// longest of the C ranges needs) so their LDS reads are in flight together.
+template <int C>
+__device__ inline void count_below(const uint32_t* S, const uint32_t (&w)[C], const int (&lo)[C],
+                                   const int (&len)[C], int (&cnt)[C]) {
+    int top = 0;
+#pragma unroll
+    for (int v = 0; v < C; ++v) {
+        top |= len[v];
+        cnt[v] = 0;
+    }
+    top = top > 0 ? 1 << (31 - __clz(top)) : 0;
+    for (int step = top; step > 0; step >>= 1) {
+#pragma unroll
+        for (int v = 0; v < C; ++v) {
+            const bool ok = cnt[v] + step <= len[v];
+            const uint32_t x = S[ok ? lo[v] + cnt[v] + step - 1 : 0];
+            if (ok && x < w[v]) cnt[v] += step;
+        }
+    }
+}
+
+// Rows of at most kLightRow entries are light; the light/heavy ranking below
+// is used while a strip's light rows hold at most kLightCap entries in all.
+constexpr int kLightRow = 64;
+constexpr int kLightCap = 512;
+
+// One listed strip of n <= 16*NT entries by a workgroup of NT threads;
+// thread t owns entries t + NT*u.  Rows sorted by column: the words go to
+// LDS (A) and each entry's place in the sorted strip is its rank among the
+// strip's words (the words of different rows never tie; equal words of one
+// row keep CSR order).  Long listed strips are mostly one or a few long rows
+// among short ones, and one binary search per (entry, other row) makes the
+// entries of a long row search every short row; instead:
+//  * the words of the light rows are gathered, in strip order, into LW (m of
+//    them); thread t takes light word t and counts the light words below it
+//    by reading all m (the same words for every lane: no bank conflicts, no
+//    dependent loads); that count is its rank among the light words, kept in
+//    LR, and its word goes to that rank in SL (the light words sorted);
+//  * an entry of a heavy row adds to its index in its row one binary search
+//    over SL, a light entry starts from its rank in LR, and every entry adds
+//    one binary search over each other heavy row.
+// With more than kLightCap light entries every row counts as heavy (one
+// search per other row).  Words and values then go to their places.  Global
+// loads (columns and values) are issued together, indices past the strip
+// clamped to its last entry, so a thread waits for memory once per strip;
+// prefetch() is called while they are in flight.  Rows not sorted: a bitonic
+// network over (word, position) keys in K, which holds pow2(n) keys.  K, A,
+// LW, LR and SL share the same LDS.
+template <int HB, int NT, typename ET, typename Prefetch>
+__device__ __forceinline__ void rank_strip_block(const StripRows& sr, int n, int bits,
+                                                 const int* __restrict__ col_ind, const ET* __restrict__ val_in,
+                                                 uint32_t* __restrict__ col_word, ET* __restrict__ val_out,
+                                                 uint64_t* K, int tid, Prefetch prefetch) {
+    constexpr int E = 16;
+    constexpr int CAP = E * NT;
+    constexpr int C = 4;  // slots searched together
+    static_assert(CAP + 3 * kLightCap <= 2 * CAP, "light lists must fit beside the words");
+    uint32_t* A = reinterpret_cast<uint32_t*>(K);
+    uint32_t* LW = A + CAP;
+    uint32_t* SL = LW + kLightCap;
+    int* LR = reinterpret_cast<int*>(SL + kLightCap);
+    const int lane = static_cast<int>(threadIdx.x) % kWave;
+    const int umax = (n + NT - 1) / NT;
+    int pos[E];
+    // Values: those of the first E/2 slots are loaded with the columns (one
+    // wait per strip for strips of up to 8*NT entries), the rest at the end.
+    ET vv[E / 2];
+    // Rows sorted by column: entry i and i + 1 of one row do not descend.
+    // Pairs inside a wave are checked before the first barrier, the pairs
+    // across waves (lane 63, next wave's lane 0) after it, from A.
+    bool bad = false;
+    {
+        uint32_t c[E];
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            pos[u] = tid + NT * u;
+            if (u < umax) {
+                const int j = sr.s0 + min(pos[u], n - 1);
+                c[u] = static_cast<uint32_t>(col_ind[j]);
+                if (u < E / 2) vv[u % (E / 2)] = val_in[j];
+            }
+        }
+        prefetch();  // the caller's loads for its next strip, in flight with these
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            if (u < umax) {  // uniform: every lane runs the row lookup and the shuffles
+                const int i = pos[u];
+                const int r = row_in_strip<HB>(sr.myrp, sr.s0 + i, 0);
+                const int rend = __shfl(sr.myrp, r + 1) - sr.s0;  // end of the entry's row
+                const uint32_t cn = __shfl_down(c[u], 1);
+                if (lane < kWave - 1 && i + 1 < n && i + 1 < rend && cn < c[u]) bad = true;
+                if (i < n) A[i] = (c[u] << bits) | static_cast<uint32_t>(r);
+            }
+        }
+    }
+    bad = __syncthreads_or(bad) != 0;  // uniform from here on
+    bool bad_across = false;
+    if (!bad && lane == kWave - 1) {
+        const uint32_t rmask = (1u << bits) - 1u;
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            const int i = tid + NT * u;
+            if (u < umax && i + 1 < n) {
+                const uint32_t w = A[i], nw = A[i + 1];
+                if ((nw & rmask) == (w & rmask) && (nw >> bits) < (w >> bits)) bad_across = true;
+            }
+        }
+    }
+    // Row table in the lanes of every wave: lane x < HB holds row x's start
+    // and length in the strip (rows past the strip: start n, length 0).
+    const int rlo = lane < sr.nr ? sr.myrp - sr.s0 : n;
+    const int rnext = __shfl(rlo, min(lane + 1, kWave - 1));
+    const int rlen = lane < HB ? rnext - rlo : 0;
+    int m = 0;  // entries in light rows
+    {
+        int v = (lane < HB && rlen <= kLightRow) ? rlen : 0;
+#pragma unroll
+        for (int off = 1; off < HB; off <<= 1) v += __shfl_xor(v, off);
+        m = __shfl(v, 0);
+    }
+    const int lt = m <= kLightCap ? kLightRow : -1;  // rows of at most lt entries are light
+    if (lt < 0) m = 0;
+    const bool rlight = lane < HB && rlen <= lt;
+    int rls = rlight ? rlen : 0;  // row's first index in LW: exclusive prefix over the lanes
+#pragma unroll
+    for (int off = 1; off < HB; off <<= 1) {
+        const int t = __shfl_up(rls, off);
+        if (lane >= off) rls += t;
+    }
+    rls -= rlight ? rlen : 0;
+    const uint64_t heavy = ballot(lane < HB && rlen > lt && rlen > 0);
+    if (!bad && m > 0) {  // uniform
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            if (u < umax) {  // uniform: every lane runs the shuffles
+                const int i = tid + NT * u;
+                const uint32_t w = i < n ? A[i] : 0u;
+                const int r = static_cast<int>(w & static_cast<uint32_t>(HB - 1));
+                const int lo = __shfl(rlo, r), ls = __shfl(rls, r), lg = __shfl(rlight ? 1 : 0, r);
+                if (i < n && lg) LW[ls + i - lo] = w;
+            }
+        }
+    }
+    if (!bad) bad = __syncthreads_or(bad_across) != 0;
+    if (!bad) {
+        if (m > 0) {
+            // Rank of light word t among the light words; LW is 16-byte aligned
+            // and read four words at a time (the same words in every lane).
+            const uint4* LW4 = reinterpret_cast<const uint4*>(LW);
+            for (int t = tid; t < m; t += NT) {
+                const uint32_t w = LW[t];
+                int cnt = 0;
+                const auto add = [&](uint32_t a, int j) { cnt += (a < w || (a == w && j < t)) ? 1 : 0; };
+                int j = 0;
+                for (; j + 8 <= m; j += 8) {
+                    const uint4 p = LW4[j / 4], q = LW4[j / 4 + 1];
+                    add(p.x, j); add(p.y, j + 1); add(p.z, j + 2); add(p.w, j + 3);
+                    add(q.x, j + 4); add(q.y, j + 5); add(q.z, j + 6); add(q.w, j + 7);
+                }
+                for (; j < m; ++j) add(LW[j], j);
+                LR[t] = cnt;
+                SL[cnt] = w;
+            }
+            __syncthreads();
+        }
+        // Places.
+#pragma unroll
+        for (int u0 = 0; u0 < E; u0 += C) {
+            if (u0 >= umax) break;
+            uint32_t w[C];
+            int r[C], lo[C], len[C], cnt[C];
+            bool live[C];
+#pragma unroll
+            for (int v = 0; v < C; ++v) {
+                const int i = tid + NT * (u0 + v);
+                live[v] = i < n;
+                w[v] = live[v] ? A[i] : 0u;
+                r[v] = static_cast<int>(w[v] & static_cast<uint32_t>(HB - 1));
+                const int rl = __shfl(rlo, r[v]), ls = __shfl(rls, r[v]), lg = __shfl(rlight ? 1 : 0, r[v]);
+                const bool hv = live[v] && !lg;
+                if (live[v]) pos[u0 + v] = hv ? i - rl : LR[ls + i - rl];
+                lo[v] = 0;
+                len[v] = hv ? m : 0;
+            }
+            count_below<C>(SL, w, lo, len, cnt);
+#pragma unroll
+            for (int v = 0; v < C; ++v) pos[u0 + v] += cnt[v];
+            for (uint64_t hm = heavy; hm; hm &= hm - 1) {  // uniform
+                const int x = __ffsll(static_cast<unsigned long long>(hm)) - 1;
+                const int xlo = __shfl(rlo, x), xlen = __shfl(rlen, x);
+#pragma unroll
+                for (int v = 0; v < C; ++v) {
+                    lo[v] = xlo;
+                    len[v] = (live[v] && x != r[v]) ? xlen : 0;
+                }
+                count_below<C>(A, w, lo, len, cnt);
+#pragma unroll
+                for (int v = 0; v < C; ++v) pos[u0 + v] += cnt[v];
+            }
+        }
+        ET vl[E / 2];
+#pragma unroll
+        for (int u = E / 2; u < E; ++u)
+            if (u < umax) vl[u - E / 2] = val_in[sr.s0 + min(tid + NT * u, n - 1)];
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            const int i = tid + NT * u;
+            if (u < umax && i < n && static_cast<unsigned>(pos[u]) < static_cast<unsigned>(n)) {
+                col_word[sr.s0 + pos[u]] = A[i];
+                val_out[sr.s0 + pos[u]] = u < E / 2 ? vv[u % (E / 2)] : vl[u % (E / 2)];
+            }
+        }
+    } else {
+        const int P = pow2_at_least(n);
+        // P is a multiple of 64, so every lane of a wave takes each trip of
+        // this loop: the row lookup's cross-lane reads see all lanes.
+        for (int i = tid; i < P; i += NT) {
+            const int r = row_in_strip<HB>(sr.myrp, sr.s0 + i, 0);
+            uint64_t key = ~0ull;
+            if (i < n)
+                key = (static_cast<uint64_t>((static_cast<uint32_t>(col_ind[sr.s0 + i]) << bits) |
+                                             static_cast<uint32_t>(r))
+                       << 32) |
+                      static_cast<uint32_t>(i);
+            K[i] = key;
+        }
+        __syncthreads();
+        bitonic_sort(K, P, tid, NT, [] { __syncthreads(); });
+        for (int i = tid; i < n; i += NT) {
+            const uint64_t kk = K[i];
+            col_word[sr.s0 + i] = static_cast<uint32_t>(kk >> 32);
+            val_out[sr.s0 + i] = val_in[sr.s0 + static_cast<int>(static_cast<uint32_t>(kk))];
+        }
+    }
+}
+
+// Row pointers of strip `strip` for lane <= rows of the strip (INT_MAX past
+// them), as load_strip_rows reads them.
+__device__ inline int strip_row_ptr(int strip, int rows, int height, const int* __restrict__ row_ptr, int lane) {
+    const int r0 = strip * height;
+    return lane <= min(height, rows - r0) ? row_ptr[r0 + lane] : INT_MAX;
+}
+
+// Sorted conversion of the listed long strips (more than kWaveSortCap
+// entries): one 1024-thread workgroup per CU; workgroup b takes list entry b
+// first, then the next untaken entry of a shared counter (ws_count[2], zero at
+// launch), so strips of very different lengths still spread evenly.  In LDS
+// when the strip fits (n <= kBlockSortCap, rank_strip_block), else in the
+// strip's own slice of the workspace [2*s0, 2*s1) (sort_strip_block).  A
+// strip costs a chain of dependent global loads (list entry, row pointers,
+// then entries); the next strip's list entry and row pointers are loaded
+// while the current one is sorted.
 template <int HB, typename ET>
 __global__ __launch_bounds__(kBlockSortThreads) void sort_list_block_kernel(
     int rows, int height, int bits, const int* __restrict__ row_ptr, const int* __restrict__ col_ind,
     const ET* __restrict__ val_in, uint32_t* __restrict__ col_word, ET* __restrict__ val_out,
-    const int* __restrict__ ws_count, const int* __restrict__ ws_big, uint64_t* __restrict__ gkeys) {
+    int* __restrict__ ws_count, const int* __restrict__ ws_big, uint64_t* __restrict__ gkeys) {
     __shared__ uint64_t skeys[kBlockSortCap];
     __shared__ int rt[HB + 1];
+    __shared__ int taken[2];
     const int tid = static_cast<int>(threadIdx.x);
     const int lane = lane_id();
     const int wave = tid / kWave;
     const int count = ws_count[1];
-    for (int item = blockIdx.x; item < count; item += gridDim.x) {
-        const StripRows sr = load_strip_rows(ws_big[item], rows, height, row_ptr, lane);
+    int item = static_cast<int>(blockIdx.x);
+    if (item >= count) return;
+    if (tid == 0) taken[0] = static_cast<int>(gridDim.x) + atomicAdd(&ws_count[2], 1);
+    int strip = ws_big[item];
+    int myrp = strip_row_ptr(strip, rows, height, row_ptr, lane);
+    __syncthreads();
+    int next = taken[0];
+    for (int k = 1; item < count; ++k) {
+        // The entry after `next` is taken now and read after this strip's
+        // last barrier (taken[] alternates, so it is not overwritten early).
+        if (tid == 0 && next < count) taken[k & 1] = static_cast<int>(gridDim.x) + atomicAdd(&ws_count[2], 1);
+        StripRows sr;
+        sr.r0 = strip * height;
+        sr.nr = min(height, rows - sr.r0);
+        sr.myrp = myrp;
+        sr.s0 = __shfl(myrp, 0);
+        sr.s1 = __shfl(myrp, sr.nr);
         const int n = sr.s1 - sr.s0;
-        if (n <= kBlockSortCap)
-            sort_strip_block<HB, ET>(sr, n, bits, col_ind, val_in, col_word, val_out, skeys, false, rt, tid, wave,
-                                     lane);
-        else
+        const int nstrip = next < count ? ws_big[next] : 0;
+        int nmyrp = INT_MAX;
+        const auto prefetch = [&] {
+            if (next < count) nmyrp = strip_row_ptr(nstrip, rows, height, row_ptr, lane);
+        };
+        if (n <= kBlockSortCap) {
+            rank_strip_block<HB, kBlockSortThreads, ET>(sr, n, bits, col_ind, val_in, col_word, val_out, skeys,
+                                                        tid, prefetch);
+        } else {
+            prefetch();
             sort_strip_block<HB, ET>(sr, n, bits, col_ind, val_in, col_word, val_out,
                                      gkeys + 2 * static_cast<size_t>(sr.s0), true, rt, tid, wave, lane);
+        }
         __syncthreads();  // the next item reuses skeys and rt
+        item = next;
+        next = next < count ? taken[k & 1] : count;
+        strip = nstrip;
+        myrp = nmyrp;
     }
 }
 
@@ -1032,6 +1314,16 @@ struct Conv {
     int rows, strips, height, bits, nnz;
 };
 
+// The listed strips of more than kWaveSortCap entries: one workgroup per CU.
+template <int HB, typename ET>
+void launch_sort_lists_big(const Conv& cv, const FromCsrWorkspaceLayout& L, const int* row_ptr, const int* col_ind,
+                           const ET* vin, uint32_t* col_word, ET* vout, int* ws_count, const int* ws_big,
+                           uint64_t* gkeys, hipStream_t stream) {
+    const int g = static_cast<int>(L.big_cap < kBlockSortGrid ? L.big_cap : kBlockSortGrid);
+    hipLaunchKernelGGL((sort_list_block_kernel<HB, ET>), dim3(g), dim3(kBlockSortThreads), 0, stream, cv.rows,
+                       cv.height, cv.bits, row_ptr, col_ind, vin, col_word, vout, ws_count, ws_big, gkeys);
+}
+
 template <int G, int E, int HB, typename ET>
 hipError_t from_csr_g(const Conv& cv, const int* row_ptr, const int* col_ind, const void* val_in,
                       int* strip_ptr, uint32_t* col_word, void* val_out, void* workspace, hipStream_t stream) {
@@ -1046,7 +1338,7 @@ hipError_t from_csr_g(const Conv& cv, const int* row_ptr, const int* col_ind, co
     int* ws_small = reinterpret_cast<int*>(ws + L.small_off);
     int* ws_big = reinterpret_cast<int*>(ws + L.big_off);
     auto* gkeys = reinterpret_cast<uint64_t*>(ws + L.global_off);
-    hipLaunchKernelGGL(set_ints_kernel, dim3(1), dim3(64), 0, stream, ws_count, 2, 0);
+    hipLaunchKernelGGL(set_ints_kernel, dim3(1), dim3(64), 0, stream, ws_count, 3, 0);
     hipLaunchKernelGGL((from_csr_group_kernel<HB, G, E, ET>), dim3(blocks), dim3(kConvThreads), 0, stream,
                        cv.rows, cv.strips, cv.height, cv.bits, cv.nnz, row_ptr, col_ind, vin, strip_ptr, col_word,
                        vout, ws_count, ws_small, ws_big);
@@ -1054,9 +1346,7 @@ hipError_t from_csr_g(const Conv& cv, const int* row_ptr, const int* col_ind, co
     const int g1 = static_cast<int>(small_blocks < 1024 ? small_blocks : 1024);
     hipLaunchKernelGGL((sort_list_wave_kernel<HB, ET>), dim3(g1), dim3(kConvThreads), 0, stream, cv.rows, cv.height,
                        cv.bits, row_ptr, col_ind, vin, col_word, vout, ws_count, ws_small);
-    const int g2 = static_cast<int>(L.big_cap < 512 ? L.big_cap : 512);
-    hipLaunchKernelGGL((sort_list_block_kernel<HB, ET>), dim3(g2), dim3(kBlockSortThreads), 0, stream, cv.rows,
-                       cv.height, cv.bits, row_ptr, col_ind, vin, col_word, vout, ws_count, ws_big, gkeys);
+    launch_sort_lists_big<HB, ET>(cv, L, row_ptr, col_ind, vin, col_word, vout, ws_count, ws_big, gkeys, stream);
     return hipGetLastError();
 }
 
@@ -1075,13 +1365,11 @@ hipError_t from_csr_bucket(const Conv& cv, const int* row_ptr, const int* col_in
     int* ws_small = reinterpret_cast<int*>(ws + L.small_off);
     int* ws_big = reinterpret_cast<int*>(ws + L.big_off);
     auto* gkeys = reinterpret_cast<uint64_t*>(ws + L.global_off);
-    hipLaunchKernelGGL(set_ints_kernel, dim3(1), dim3(64), 0, stream, ws_count, 2, 0);
+    hipLaunchKernelGGL(set_ints_kernel, dim3(1), dim3(64), 0, stream, ws_count, 3, 0);
     hipLaunchKernelGGL((from_csr_bucket_kernel<HB, E, ET>), dim3(blocks), dim3(kConvThreads), 0, stream, cv.rows,
                        cv.strips, cv.height, cv.bits, cv.nnz, row_ptr, col_ind, vin, strip_ptr, col_word, vout,
                        ws_count, ws_small, ws_big);
-    const int g2 = static_cast<int>(L.big_cap < 512 ? L.big_cap : 512);
-    hipLaunchKernelGGL((sort_list_block_kernel<HB, ET>), dim3(g2), dim3(kBlockSortThreads), 0, stream, cv.rows,
-                       cv.height, cv.bits, row_ptr, col_ind, vin, col_word, vout, ws_count, ws_big, gkeys);
+    launch_sort_lists_big<HB, ET>(cv, L, row_ptr, col_ind, vin, col_word, vout, ws_count, ws_big, gkeys, stream);
     return hipGetLastError();
 }
 

@@ -308,3 +308,64 @@ def test_tall_strips_bucket_sort(C, height, dtype):
     D = _rows_matrix(rng, rows, cols, k, lambda i, n: np.unique(np.concatenate(
         [np.clip(i + rng.integers(-512, 513, max(1, 7 * n // 10)), 0, cols - 1), rng.integers(0, cols, n // 3)])))
     check_from_csr(C, D, height, True, dtype)
+
+
+@pytest.mark.parametrize("height", [2, 3, 7, 12, 24, 32])
+@pytest.mark.parametrize("dtype", ["f64", "bf16"])
+def test_workgroup_merge_strips(C, height, dtype):
+    """Listed strips of 1025..16384 entries with rows sorted by column (the
+    workgroup's merge of the row runs): one dominant row among short ones,
+    rows of equal length, repeated columns inside a row (ties keep CSR
+    order), empty rows inside a strip, a strip of exactly 16384 entries and
+    one of 16385 (the workspace path), columns in a band around the diagonal
+    plus scattered ones (the skewed workload's shape)."""
+    rng = np.random.default_rng(100 + height)
+    strips = 24
+    rows, cols = strips * height - 1, 1 << 21
+    k = rng.poisson(6, rows)
+    k[rng.random(rows) < 0.2] = 0
+    for s in range(strips):
+        r0 = s * height
+        if s % 4 == 0:
+            k[r0 + (s // 4) % height] = int(rng.integers(1100, 12000))       # one dominant row
+        elif s % 4 == 1:
+            k[r0: r0 + height] = 16384 // height + 40                    # rows of equal length
+    k = k[:rows]
+    # strip 2: exactly 16384 entries, strip 3: 16385
+    for s, want in ((2, 16384), (3, 16385)):
+        seg = k[s * height:(s + 1) * height]
+        seg[:] = want // height
+        seg[0] += want - int(seg.sum())
+    assert int(k[2 * height:3 * height].sum()) == 16384 and int(k[3 * height:4 * height].sum()) == 16385
+
+    def cols_of(i, n):
+        near = np.clip(i * (cols // rows) + rng.integers(-512, 513, n), 0, cols - 1)
+        far = rng.integers(0, cols, n)
+        c = np.where(rng.random(n) < 0.7, near, far)
+        if i % 3 == 0:
+            c[: n // 4] = c[0]                                           # repeated columns
+        return c
+    A = _rows_matrix(rng, rows, cols, k, cols_of)
+    M, hv = check_from_csr(C, A, height, True, dtype)
+    check_round_trip(C, A, M, hv)
+
+
+@pytest.mark.parametrize("height", [1, 2, 32])
+def test_long_strip_single_descent(C, height):
+    """Listed strips whose rows are sorted but for one descending pair, placed
+    where the workgroup sort's check pairs entries across waves (entry 63|64,
+    1023|1024, 1087|1088 of the strip) or inside a wave (500|501): each strip
+    must still come out in (column, row, CSR order)."""
+    rng = np.random.default_rng(7 + height)
+    cuts = [63, 1023, 1087, 500]
+    rows, cols = len(cuts) * height, 1 << 20
+    k = np.zeros(rows, np.int64)
+    k[::height] = 3000                       # one long first row per strip
+    if height > 1:
+        k[1::height] = 5
+    A = _rows_matrix(rng, rows, cols, k, lambda i, n: rng.choice(cols, size=n, replace=False))
+    for s, c in enumerate(cuts):
+        a = A.row_ptr[s * height] + c        # a pair inside the long row
+        A.col_ind[a], A.col_ind[a + 1] = A.col_ind[a + 1], A.col_ind[a]
+    M, hv = check_from_csr(C, A, height, True)
+    check_round_trip(C, A, M, hv)
