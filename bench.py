@@ -21,7 +21,7 @@ the same K steps are then run in fp32.  `ms_per_step` is the fp64 step.
 
 Prints one short JSON line on stdout (headline, roofline, CPU baseline and a
 one-line summary of every report); the full sweep and report tables go to the
-detail file (--detail, default gpurun_out/bench_detail.json).  Progress goes
+detail file (--detail, default bench_detail.json in the working directory).  Progress goes
 to stderr.
 """
 from __future__ import annotations
@@ -72,7 +72,7 @@ def parse():
                    help="run only that report (for profiling) and print it as one JSON line")
     p.add_argument("--batched-fixed", default=None,
                    help="skip the batched autotuner: dtype=height:tile_nnz:group:blocks_per_cu[,dtype=...]")
-    p.add_argument("--detail", default=None, help="path of the detail JSON (default gpurun_out/bench_detail.json)")
+    p.add_argument("--detail", default=None, help="path of the detail JSON (default bench_detail.json)")
     p.add_argument("--copy-calib", action="store_true",
                    help="only run three plain 1 GiB device-to-device copies (calibrates HBM byte counters)")
     return p.parse_args()
@@ -588,14 +588,29 @@ def compact_line(res: dict) -> str:
     for k in ("spmv", "step", "ceiling"):
         if k in res:
             line[k] = res[k]
-    if summ:
-        line["reports"] = _round_floats(summ)
+    summ = _round_floats(summ)
     if "detail_file" in res:
         line["detail_file"] = res["detail_file"]
-    txt = json.dumps(line, separators=(",", ":"))
-    if len(txt) > 4000:
-        raise ValueError(f"bench line is {len(txt)} characters (limit 4000)")
+    # Report summaries are dropped, least important first, until the line
+    # fits in LINE_SOFT_LIMIT characters (every report stays in the detail
+    # file); only a line too long without any of them is refused.
+    for drop in REPORT_DROP_ORDER + [None]:
+        if summ:
+            line["reports"] = summ
+        txt = json.dumps(line, separators=(",", ":"))
+        if len(txt) <= LINE_SOFT_LIMIT or not summ:
+            break
+        summ = {k: v for k, v in summ.items() if k != drop}
+        line.pop("reports", None)
+    if len(txt) > LINE_HARD_LIMIT:
+        raise ValueError(f"bench line is {len(txt)} characters (limit {LINE_HARD_LIMIT})")
     return txt
+
+
+LINE_SOFT_LIMIT = 3800
+LINE_HARD_LIMIT = 4000
+REPORT_DROP_ORDER = ["padded_small_mu", "padded", "model_eq52_f64", "structured", "residual_refinement",
+                     "selector", "batched", "precision_zipf"]
 
 
 def padded_small_mu_report():
@@ -910,9 +925,10 @@ def main():
     detail = dict(res)
     detail.update({"sweep": sweep, "kernel_src": kernel_source_hash(), "step_detail": {"f64": step64, "f32": step32},
                    "spmv_detail": {"f64": spmv64, "f32": spmv32}})
-    path = args.detail or os.path.join(ROOT, "gpurun_out", "bench_detail.json")
+    path = args.detail or "bench_detail.json"
     try:
-        os.makedirs(os.path.dirname(path), exist_ok=True)
+        if os.path.dirname(path):
+            os.makedirs(os.path.dirname(path), exist_ok=True)
         with open(path, "w") as f:
             json.dump(detail, f, indent=1)
         res["detail_file"] = os.path.relpath(path, ROOT)

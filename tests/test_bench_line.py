@@ -59,7 +59,7 @@ def _canned():
                  "f32": {"ms": 0.7, "gbs": 2000.0},
                  "kernels_f64_ms": {"from_csr_sorted": 0.44, "colblock_plan": 0.03, "spmv": 0.151, "to_csr": 0.16}},
         "ceiling": {"stream_read_gbs": 6219.5, "gathers_per_s": 106.3, "gather_floor_over_spmv": 0.86},
-        "extras": ex, "detail_file": "gpurun_out/bench_detail.json",
+        "extras": ex, "detail_file": "bench_detail.json",
     }
 
 
@@ -104,3 +104,13 @@ def test_baseline_build_matches_oracle_bits():
     E = synth.Csr(5, 3, np.zeros(6, np.int32), np.zeros(0, np.int32), np.zeros(0))
     y, _ = oracle.csr_spmv_par(E.row_ptr, E.col_ind, E.val, np.ones(3), 4, lib=lib)
     assert np.all(y == 0)
+
+
+def test_line_drops_reports_before_growing():
+    r = _canned()
+    r["extras"]["structured"] = {f"m{i}": {"f64": {"eta_plus": 0.5}, "f32": {"eta_plus": 0.6}} for i in range(60)}
+    txt = bench.compact_line(r)
+    assert len(txt) <= bench.LINE_SOFT_LIMIT, len(txt)
+    d = json.loads(txt)
+    assert "structured" not in d.get("reports", {})
+    assert "precision_zipf" in d["reports"] and "batched" in d["reports"]
