@@ -369,3 +369,32 @@ def test_long_strip_single_descent(C, height):
         A.col_ind[a], A.col_ind[a + 1] = A.col_ind[a + 1], A.col_ind[a]
     M, hv = check_from_csr(C, A, height, True)
     check_round_trip(C, A, M, hv)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_long_strips_random_mixes(C, seed):
+    """Listed strips (past 1024 entries) from random mixes of row lengths: empty
+    rows, short rows (the gathered short-row list, up to and past its 512-entry
+    capacity), rows just over the 64-entry short-row limit, and long rows (one
+    or several per strip); repeated columns inside rows; heights 2..32 with
+    ragged last strips; every value type."""
+    rng = np.random.default_rng(1000 + seed)
+    height = int(rng.choice([2, 3, 8, 16, 24, 32]))
+    dtype = ["f64", "f32", "bf16"][seed % 3]
+    strips = 20
+    rows, cols = strips * height - int(rng.integers(0, height)), 1 << 21
+    kinds = rng.choice(5, size=rows, p=[0.15, 0.45, 0.15, 0.1, 0.15])
+    lo_hi = [(0, 1), (1, 11), (20, 65), (65, 200), (1000, 6000)]
+    k = np.array([rng.integers(*lo_hi[t]) for t in kinds], dtype=np.int64)
+    if height >= 16:                      # strip 0: short rows past the 512-entry list
+        k[:height] = 40
+        k[0] = 2000
+
+    def cols_of(i, n):
+        c = rng.integers(0, cols, n)
+        if rng.random() < 0.3 and n > 2:
+            c[: n // 3] = c[0]                                           # repeated columns
+        return c
+    A = _rows_matrix(rng, rows, cols, k, cols_of)
+    M, hv = check_from_csr(C, A, height, True, dtype)
+    check_round_trip(C, A, M, hv)
