@@ -159,14 +159,26 @@ __global__ __launch_bounds__(256) void colblock_plan_kernel(int strips, int bits
     const int strip = xcd_logical_block(blockIdx.x, gridDim.x) * 4 + wave;
     if (strip >= strips) return;
     const int s0 = strip_ptr[strip], s1 = strip_ptr[strip + 1];
+    // U rounds of 64 words are loaded before any is counted, so a strip of up
+    // to 64*U entries costs one memory round trip, not one per round.
+    constexpr int U = 8;
     int below = 0;
-    for (int base = s0; base < s1; base += kWave) {
-        const int e = base + lane;
-        const int c = e < s1 ? static_cast<int>(word[e] >> bits) : 0x7fffffff;
-        const int blk = c / bw;
-        for (int b = 1; b < nb; ++b) {
-            const uint64_t m = ballot(e < s1 && blk < b);
-            if (lane == b - 1) below += __popcll(m);
+    for (int base = s0; base < s1; base += U * kWave) {
+        uint32_t w[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = base + u * kWave + lane;
+            w[u] = e < s1 ? word[e] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (base + u * kWave >= s1) break;  // uniform
+            const int e = base + u * kWave + lane;
+            const int blk = e < s1 ? static_cast<int>(w[u] >> bits) / bw : nb;
+            for (int b = 1; b < nb; ++b) {
+                const uint64_t m = ballot(blk < b);
+                if (lane == b - 1) below += __popcll(m);
+            }
         }
     }
     if (lane < nb - 1) split[static_cast<size_t>(strip) * (nb - 1) + lane] = s0 + below;
