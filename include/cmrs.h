@@ -157,7 +157,9 @@ size_t cmrs_to_csr_workspace(const cmrs_mat_t *A);
  *   row_ptr_out[rows+1], col_ind_out[nnz], val_out[nnz]   CSR output (device);
  *   no output may overlap an input.
  * For an unsorted CMRS matrix this reproduces the CSR it came from bit for
- * bit; for a sorted one, columns come out ascending inside each row.
+ * bit; for a sorted one, columns come out ascending inside each row.  A word
+ * whose RowInStrip names no row of its strip is invalid input: it is dropped,
+ * nothing is written outside the outputs, and their contents are unspecified.
  */
 cmrs_status_t cmrs_to_csr(const cmrs_mat_t *A, int32_t *row_ptr_out, int32_t *col_ind_out,
                           void *val_out, void *workspace, size_t workspace_bytes,

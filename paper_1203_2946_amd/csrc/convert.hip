@@ -636,6 +636,7 @@ __device__ inline RunRound run_round(int myp, int b, int e1, uint32_t w, uint32_
 constexpr int kToCsrWaves = 4;
 constexpr int kToCsrThreads = kToCsrWaves * kWave;
 constexpr int kLongRun = 2048;
+constexpr int kToCsrStage = 640;
 
 // One run of the CMRS -> CSR kernel: strips [S, S + nsw), rows [r0, r0 +
 // nrow), entries [e0, e1); lane t <= nsw holds StripPtr[S + t] in myp.
@@ -673,13 +674,21 @@ __device__ inline ToCsrRun to_csr_run(int run, int ns, int strips, int rows, int
 // its ranks, and each wave scatters its slice.  Every wave reads the lengths
 // of the workgroup's runs and so takes the same barrier-or-not decision; a
 // workgroup without a long run has no barrier.
-template <typename ET>
-__global__ __launch_bounds__(kToCsrThreads) __attribute__((amdgpu_waves_per_eu(8))) void to_csr_rows_kernel(
+template <typename ET, bool STAGE>
+__global__ __launch_bounds__(kToCsrThreads) __attribute__((amdgpu_waves_per_eu(STAGE ? 5 : 8))) void to_csr_rows_kernel(
     int rows, int strips, int height, int bits, int ns, const int* __restrict__ strip_ptr,
     const uint32_t* __restrict__ word, const ET* __restrict__ val, int* __restrict__ row_ptr,
     int* __restrict__ col_ind, ET* __restrict__ val_out) {
     constexpr int UF = 12, U = 8, FIT = UF * kWave;
     __shared__ int slice_cnt[kToCsrWaves][kRunRows];
+    // STAGE: a run of at most kToCsrStage entries is scattered into LDS and
+    // then written out in order (the run's CSR range is contiguous): with many
+    // rows per strip the 64 lanes of a scatter would otherwise each write into
+    // another line.  The LDS lowers the waves per SIMD from 8 to 5, which costs
+    // more than it saves at small heights and on runs of very uneven length.
+    constexpr int SCAP = STAGE ? kToCsrStage : 1;
+    __shared__ int stage_col[kToCsrWaves][SCAP];
+    __shared__ ET stage_val[kToCsrWaves][SCAP];
     const int lane = lane_id();
     const int wave = uniform(static_cast<int>(threadIdx.x) / kWave);
     const int run0 = xcd_logical_block(blockIdx.x, gridDim.x) * kToCsrWaves;
@@ -789,11 +798,38 @@ __global__ __launch_bounds__(kToCsrThreads) __attribute__((amdgpu_waves_per_eu(8
             }
             int next = row_starts(R, cnt, true);
             tc = 0;
+            const int n = R.e1 - R.e0;
+            if (STAGE && n <= SCAP) {
+                int* sc = stage_col[wave];
+                ET* sv = stage_val[wave];
 #pragma unroll
-            for (int u = 0; u < UF; ++u) {
-                if (R.e0 + u * kWave >= R.e1) break;
-                const RunRound rr = run_round(R.myp, R.e0 + u * kWave, R.e1, w[u], mask, height, R.nrow, tc);
-                scatter(R, rr, w[u], v[u], next);
+                for (int u = 0; u < UF; ++u) {
+                    if (R.e0 + u * kWave >= R.e1) break;
+                    const RunRound rr = run_round(R.myp, R.e0 + u * kWave, R.e1, w[u], mask, height, R.nrow, tc);
+                    const int src = rr.key >= 0 ? rr.key : 0;
+                    const int pos = __shfl(next, src) + __popcll(key_match(src, rr.valid, rr.kb) & lt) - R.e0;
+                    if (rr.key >= 0 && static_cast<unsigned>(pos) < static_cast<unsigned>(n)) {
+                        sc[pos] = static_cast<int>(w[u] >> bits);
+                        sv[pos] = v[u];
+                    }
+                    next += __popcll(key_match(lane, rr.valid, rr.kb));
+                }
+                wave_lds_sync();
+                // Every place of the run is written above (the rows' counts
+                // add up to n) unless a word names no row of its strip; those
+                // places keep what the stage held and are not valid output.
+                for (int i = lane; i < n; i += kWave) {
+                    col_ind[R.e0 + i] = sc[i];
+                    val_out[R.e0 + i] = sv[i];
+                }
+                wave_lds_sync();
+            } else {
+#pragma unroll
+                for (int u = 0; u < UF; ++u) {
+                    if (R.e0 + u * kWave >= R.e1) break;
+                    const RunRound rr = run_round(R.myp, R.e0 + u * kWave, R.e1, w[u], mask, height, R.nrow, tc);
+                    scatter(R, rr, w[u], v[u], next);
+                }
             }
         } else {
             int next = row_starts(R, count_range(R, R.e0, R.e1), true);
@@ -1437,7 +1473,13 @@ hipError_t to_csr_typed(const cmrs_mat_t* A, int* row_ptr, int* col_ind, void* v
     const int ns = kRunRows / A->height;
     const int runs = (strips + ns - 1) / ns;
     const int blocks = (runs + kToCsrWaves - 1) / kToCsrWaves;
-    hipLaunchKernelGGL((to_csr_rows_kernel<ET>), dim3(blocks), dim3(kToCsrThreads), 0, stream, A->rows, strips,
+    // Staged output from height 8 on, for runs of at least kToCsrStage/2.5
+    // entries on average (measured: 2^20 rows of Poisson(16), height 32: 160
+    // -> 107 us; height 2 and the skewed rows of up to 10^4 entries are faster
+    // without).
+    const bool stage = A->height >= 8 && static_cast<double>(A->nnz) >= kToCsrStage / 2.5 * runs;
+    auto kern = stage ? to_csr_rows_kernel<ET, true> : to_csr_rows_kernel<ET, false>;
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kToCsrThreads), 0, stream, A->rows, strips,
                        A->height, A->bits, ns, A->strip_ptr, A->col_word, static_cast<const ET*>(A->val), row_ptr,
                        col_ind, static_cast<ET*>(val_out));
     return hipGetLastError();

@@ -398,3 +398,24 @@ def test_long_strips_random_mixes(C, seed):
     A = _rows_matrix(rng, rows, cols, k, cols_of)
     M, hv = check_from_csr(C, A, height, True, dtype)
     check_round_trip(C, A, M, hv)
+
+
+@pytest.mark.parametrize("height", [8, 16, 32])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_to_csr_staged_runs(C, height, dtype):
+    """CMRS -> CSR where runs of rows are long enough on average for the output
+    to be staged in LDS: runs below and above the stage's 640 entries and past
+    the shared-run length (2048), empty rows, an empty run of rows, a ragged
+    last strip; sorted and unsorted strips."""
+    rng = np.random.default_rng(300 + height)
+    rows, cols = 32 * 40 + 7, 1 << 20
+    k = rng.poisson(16, rows)
+    k[rng.random(rows) < 0.1] = 0
+    k[32:64] = 0                                  # an empty run of 32 rows
+    k[96:128] = 25                                # a run of 800 entries
+    k[160] = 2500                                 # a run past 2048 entries
+    A = _rows_matrix(rng, rows, cols, k, lambda i, n: rng.choice(cols, size=n, replace=False))
+    for sort in (True, False):
+        M, hv = check_from_csr(C, A, height, sort, dtype)
+        rp2, ci2, v2 = check_round_trip(C, A, M, hv)
+        assert np.array_equal(rp2.cpu().numpy(), A.row_ptr)
