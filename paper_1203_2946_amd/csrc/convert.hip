@@ -350,6 +350,8 @@ __global__ __launch_bounds__(kConvThreads) __attribute__((amdgpu_waves_per_eu(8)
         const bool go = valid && !special;
         merge_runs_regs<HB, G, E>(A, B, rtab, wd, pos, umax, go, n, q);
         // Out from registers: each entry to its place in the sorted strip.
+        // (Staging through LDS as the tall-strip kernel does was measured
+        // slower here: 133 -> 137 us at height 2, 156 -> 164 us at height 4.)
 #pragma unroll
         for (int u = 0; u < E; ++u) {
             if (u >= umax) break;
@@ -506,19 +508,37 @@ __global__ __launch_bounds__(kConvThreads) void from_csr_bucket_kernel(
                 K[start[bs[u] >> 16] + (bs[u] & 0xffff)] = (static_cast<uint64_t>(wd[u]) << 32) | static_cast<uint32_t>(i);
         }
         wave_lds_sync();
+        int pos[E];
 #pragma unroll
         for (int u = 0; u < E; ++u) {
             const int i = lane + kWave * u;
+            pos[u] = 0;
             if (u < umax && i < n) {
                 const int bk = bs[u] >> 16;
                 const int b0 = start[bk], b1 = b0 + cnt[bk];
                 const uint64_t key = (static_cast<uint64_t>(wd[u]) << 32) | static_cast<uint32_t>(i);
-                int pos = b0;
-                for (int k = b0; k < b1; ++k) pos += K[k] < key ? 1 : 0;
-                col_word[sr.s0 + pos] = wd[u];
-                val_out[sr.s0 + pos] = v[u];
+                int p = b0;
+                for (int k = b0; k < b1; ++k) p += K[k] < key ? 1 : 0;
+                pos[u] = p;
             }
         }
+        // The strip's sorted words, then its sorted values, go through the
+        // key buffer and out in order: a scatter into the strip's range would
+        // leave partly written lines (each reaching HBM more than once).
+        wave_lds_sync();
+        uint32_t* KW = reinterpret_cast<uint32_t*>(K);
+#pragma unroll
+        for (int u = 0; u < E; ++u)
+            if (u < umax && lane + kWave * u < n) KW[pos[u]] = wd[u];
+        wave_lds_sync();
+        for (int i = lane; i < n; i += kWave) col_word[sr.s0 + i] = KW[i];
+        wave_lds_sync();
+        ET* KV = reinterpret_cast<ET*>(K);
+#pragma unroll
+        for (int u = 0; u < E; ++u)
+            if (u < umax && lane + kWave * u < n) KV[pos[u]] = v[u];
+        wave_lds_sync();
+        for (int i = lane; i < n; i += kWave) val_out[sr.s0 + i] = KV[i];
     } else {
         const int P = pow2_at_least(n);
 #pragma unroll
