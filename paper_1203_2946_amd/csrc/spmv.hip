@@ -262,12 +262,17 @@ hipError_t launch_concurrent_g(const Launch& L) {
     return hipGetLastError();
 }
 
-// Lanes per column-block run: about 8 entries per lane for the average run.
+// Lanes per column-block run: about 4 entries per lane for the average run,
+// at most 16 lanes with fp64 partials at height 32.  (Measured with 4 blocks,
+// cold, 2^20-row Poisson(16) rows: fp64 at height 8/16 204/161 us against
+// 244/190 us with 8 entries per lane; fp32 at height 32 115 against 147 us;
+// fp64 at height 32 150 us with 16 lanes, 196 with 32.)
 template <typename VT, typename XT, typename AT, int HB>
 hipError_t launch_concurrent(const Launch& L) {
     const double avg = static_cast<double>(L.A->nnz) / (static_cast<double>(L.strips) * L.nb);
     int g = 2;
-    while (g < 64 && g * 8 * 1.5 < avg) g <<= 1;
+    while (g < 64 && g * 4 * 1.5 < avg) g <<= 1;
+    if (sizeof(AT) == 8 && HB == 32 && g > 16) g = 16;
     switch (g) {
         case 2: return launch_concurrent_g<VT, XT, AT, HB, 2>(L);
         case 4: return launch_concurrent_g<VT, XT, AT, HB, 4>(L);
@@ -315,10 +320,18 @@ hipError_t dispatch(int variant, const Launch& L) {
 
 }  // namespace
 
+// Lanes per strip of the strip-group kernels: about `per` entries per lane
+// for the average strip, per = 4 up to height 8 and 8 above.  (Measured, cold
+// fp64: 2^20-row Poisson(16) rows at height 2/4/8, 268/219/199 us with 8
+// entries per lane against 221/198/188 us with 4, and the skewed 2*10^6-row
+// workload gains a little there too; at heights 16 and 32 that workload loses
+// with 4, e.g. 179 -> 235 us at height 32, where one wave then takes each
+// strip.)
 int spmv_group_width(int nnz, int strips, int hb) {
     const double avg = strips > 0 ? static_cast<double>(nnz) / strips : 0.0;
+    const int per = hb <= 8 ? 4 : 8;
     int g = 2;
-    while (g < 64 && g * 8 * 1.5 < avg) g <<= 1;
+    while (g < 64 && g * per * 1.5 < avg) g <<= 1;
     return g < hb ? hb : g;
 }
 
