@@ -41,9 +41,12 @@ __device__ inline AT reduce_rows_lds(const AT* b, int lane) {
     constexpr int PER = kWave / G;
     const int r = lane / G, q = lane % G;
     const AT* p = b + r * kWave + q * PER;
-    AT s = p[0];
+    // Group r starts at partial r mod PER and wraps, so the HB groups, which
+    // read at a stride of 64 slots, do not all hit the same LDS banks.
+    const int rot = r & (PER - 1);
+    AT s = p[rot];
 #pragma unroll
-    for (int i = 1; i < PER; ++i) s += p[i];
+    for (int i = 1; i < PER; ++i) s += p[(i + rot) & (PER - 1)];
 #pragma unroll
     for (int off = G / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off);
     return s;
@@ -139,8 +142,12 @@ __device__ inline void accumulate_run(Acc& acc, int lo, int hi, int bits, const 
 // Sum each (group g, row r) set of G partials held in LDS slots
 // ((g*HB + r)*G + q, q < G) and hand the sum to out(g, r, sum).  There are
 // S = NG*HB sums: with S <= 64, L = 64/S lanes share one sum (xor butterfly);
-// otherwise every lane takes S/64 whole sums.  out() is called by a subset of
-// the lanes and must not use cross-lane operations.
+// otherwise every lane takes S/64 whole sums.  A lane reading PER consecutive
+// slots starts at slot si mod PER of them and wraps: lanes reading at a
+// stride of PER slots would otherwise all hit the same LDS banks.  (The
+// order of the additions is fixed per sum, so results stay deterministic.)
+// out() is called by a subset of the lanes and must not use cross-lane
+// operations.
 template <int HB, int G, typename AT, typename Out>
 __device__ inline void group_reduce(const AT* b, int lane, Out out) {
     constexpr int NG = kWave / G;
@@ -150,9 +157,10 @@ __device__ inline void group_reduce(const AT* b, int lane, Out out) {
         constexpr int PER = G / L;
         const int si = lane / L, part = lane % L;
         const AT* pp = b + si * G + part * PER;
-        AT s = pp[0];
+        const int rot = si & (PER - 1);
+        AT s = pp[rot];
 #pragma unroll
-        for (int i = 1; i < PER; ++i) s += pp[i];
+        for (int i = 1; i < PER; ++i) s += pp[(i + rot) & (PER - 1)];
 #pragma unroll
         for (int off = L / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off);
         if (part == 0) out(si / HB, si % HB, s);
@@ -162,9 +170,10 @@ __device__ inline void group_reduce(const AT* b, int lane, Out out) {
         for (int i = 0; i < K; ++i) {
             const int si = lane + kWave * i;
             const AT* pp = b + si * G;
-            AT s = pp[0];
+            const int rot = si & (G - 1);
+            AT s = pp[rot];
 #pragma unroll
-            for (int j = 1; j < G; ++j) s += pp[j];
+            for (int j = 1; j < G; ++j) s += pp[(j + rot) & (G - 1)];
             out(si / HB, si % HB, s);
         }
     }
