@@ -262,17 +262,15 @@ hipError_t launch_concurrent_g(const Launch& L) {
     return hipGetLastError();
 }
 
-// Lanes per column-block run: about 4 entries per lane for the average run,
-// at most 16 lanes with fp64 partials at height 32.  (Measured with 4 blocks,
-// cold, 2^20-row Poisson(16) rows: fp64 at height 8/16 204/161 us against
-// 244/190 us with 8 entries per lane; fp32 at height 32 115 against 147 us;
-// fp64 at height 32 150 us with 16 lanes, 196 with 32.)
+// Lanes per column-block run: about 4 entries per lane for the average run.
+// (Measured with 4 blocks, cold, 2^20-row Poisson(16) rows: fp64 at height
+// 8/16/32 204/161/131 us against 244/190/145 us with 8 entries per lane;
+// fp32 at height 32 115 against 147 us.)
 template <typename VT, typename XT, typename AT, int HB>
 hipError_t launch_concurrent(const Launch& L) {
     const double avg = static_cast<double>(L.A->nnz) / (static_cast<double>(L.strips) * L.nb);
     int g = 2;
     while (g < 64 && g * 4 * 1.5 < avg) g <<= 1;
-    if (sizeof(AT) == 8 && HB == 32 && g > 16) g = 16;
     switch (g) {
         case 2: return launch_concurrent_g<VT, XT, AT, HB, 2>(L);
         case 4: return launch_concurrent_g<VT, XT, AT, HB, 4>(L);
