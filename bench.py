@@ -13,7 +13,8 @@ Before the timed steps every strip height 1..32 and SpMV schedule is measured
 with the paper's protocol (11 calls, the longest dropped, mean and std of the
 rest; Sec. 6.3), cold (L2 and MALL flushed by a 1 GiB write before each call)
 and warm, for fp64 and fp32.  Unless --height / --schedule are given, the timed
-steps of each precision use the (height, schedule) with the fastest cold SpMV.
+steps of each precision use the (height, schedule) whose SpMV is fastest by
+the mean of its cold and warm times.
 
 The headline `value` is the fp64 SpMV's beta+ rate (Eq. 6.1: bytes with x read
 once, over the SpMV's time, from HIP events inside the K timed fp64 steps);
@@ -805,15 +806,17 @@ def main():
                     del P
 
     def choose(dt):
-        """(height, schedule) of the timed steps: the fastest cold SpMV of the
-        sweep unless --height / --schedule fix them."""
+        """(height, schedule) of the timed steps: the fastest SpMV of the sweep
+        by the mean of its cold and warm times (the steps run it right after
+        the conversion, between those two conditions), unless --height /
+        --schedule fix them."""
         cand = [r for r in sweep if r["dtype"] == dt]
         if args.height and args.schedule:
             return args.height, args.schedule
         pool = [r for r in cand if (not args.height or r["height"] == args.height)
                 and (not args.schedule or r["schedule"] == args.schedule)]
         if pool:
-            best = min(pool, key=lambda r: r["spmv_cold_ms"])
+            best = min(pool, key=lambda r: r["spmv_cold_ms"] + r["spmv_warm_ms"])
             return best["height"], best["schedule"]
         return args.height or 32, args.schedule or "colblock4"
 
