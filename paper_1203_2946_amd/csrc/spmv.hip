@@ -323,8 +323,8 @@ hipError_t dispatch(int variant, const Launch& L) {
 // fp64: 2^20-row Poisson(16) rows at height 2/4/8, 268/219/199 us with 8
 // entries per lane against 221/198/188 us with 4, and the skewed 2*10^6-row
 // workload gains a little there too; at heights 16 and 32 that workload loses
-// with 4, e.g. 179 -> 235 us at height 32, where one wave then takes each
-// strip.)
+// with 4, e.g. 142 -> 147 us at height 16 and 162 -> 185 us at height 32,
+// where one wave then takes each strip.)
 int spmv_group_width(int nnz, int strips, int hb) {
     const double avg = strips > 0 ? static_cast<double>(nnz) / strips : 0.0;
     const int per = hb <= 8 ? 4 : 8;
