@@ -249,12 +249,20 @@ __device__ inline int used_slots(int n) {
     return uniform((m + G - 1) / G);
 }
 
+// Strips past a group's capacity of at most this many entries are sorted by
+// the group kernel's wave itself, longer ones listed for the list kernels.
+// (Listing every such strip spreads the work but costs a wave per strip;
+// measured on the skewed 2*10^6-row workload, sorted conversion at height
+// 2/4/8: 256/275/298 us inline up to 512 entries, 243/257/273 us up to 256,
+// 383/289/272 us listing all; the benchmark matrix is unchanged.)
+constexpr int kInlineSortMax = 256;
+
 // CSR -> CMRS with the reorder, for strips of at most G*E entries, G lanes
-// per strip.  Writes strip_ptr too.  Longer strips of at most kWave*E entries
-// and strips with unsorted rows are sorted by the whole wave afterwards in the
-// wave's LDS slice; still longer ones go to the workspace lists
-// (ws_count[0] / ws_small: at most kWaveSortCap entries; ws_count[1] /
-// ws_big: longer).  No output may alias an input.
+// per strip.  Writes strip_ptr too.  Longer strips of at most kInlineSortMax
+// entries (and no more than kWave*E), and strips with unsorted rows as short,
+// are sorted by the whole wave afterwards in the wave's LDS slice; longer ones
+// go to the workspace lists (ws_count[0] / ws_small: at most kWaveSortCap
+// entries; ws_count[1] / ws_big: longer).  No output may alias an input.
 template <int HB, int G, int E, typename ET>
 __global__ __launch_bounds__(kConvThreads) __attribute__((amdgpu_waves_per_eu(8))) void from_csr_group_kernel(
     int rows, int strips, int height, int bits, int nnz, const int* __restrict__ row_ptr,
@@ -340,8 +348,9 @@ __global__ __launch_bounds__(kConvThreads) __attribute__((amdgpu_waves_per_eu(8)
         }
         const bool gbad = (ballot(bad) & group_mask(gbase, G)) != 0;
         special = special || (valid && gbad);
-        constexpr int WCAP = kWave * E;
-        if (valid && special && q == 0 && n > WCAP) {
+        constexpr int WCAP = kWave * E;  // what sort_strip_mid<HB, E> holds
+        constexpr int INLINE = kInlineSortMax < WCAP ? kInlineSortMax : WCAP;
+        if (valid && special && q == 0 && n > INLINE) {
             if (n <= kWaveSortCap)
                 ws_small[atomicAdd(&ws_count[0], 1)] = strip;
             else
@@ -361,7 +370,7 @@ __global__ __launch_bounds__(kConvThreads) __attribute__((amdgpu_waves_per_eu(8)
             }
         }
         wave_lds_sync();  // the wave's slice is reused below
-        uint64_t mids = ballot(valid && special && q == 0 && n <= WCAP);
+        uint64_t mids = ballot(valid && special && q == 0 && n <= INLINE);
         while (mids) {
             const int leader = __ffsll(static_cast<unsigned long long>(mids)) - 1;
             mids &= mids - 1;
