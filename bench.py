@@ -12,9 +12,10 @@ preallocated and resident in HBM.
 Before the timed steps every strip height 1..32 and SpMV schedule is measured
 with the paper's protocol (11 calls, the longest dropped, mean and std of the
 rest; Sec. 6.3), cold (L2 and MALL flushed by a 1 GiB write before each call)
-and warm, for fp64 and fp32.  Unless --height / --schedule are given, the timed
-steps of each precision use the (height, schedule) whose SpMV is fastest by
-the mean of its cold and warm times.
+and warm, for fp64 and fp32.  Unless --height / --schedule are given, the three
+(height, schedule) pairs whose SpMV is fastest by the mean of its cold and
+warm times each run 5 untimed trial steps, and the timed steps of each
+precision use the one whose SpMV is fastest inside the step.
 
 The headline `value` is the fp64 SpMV's beta+ rate (Eq. 6.1: bytes with x read
 once, over the SpMV's time, from HIP events inside the K timed fp64 steps);
@@ -805,25 +806,21 @@ def main():
                         f"eta+ {r['eta_plus_cold']:.3f}) warm {wm * 1e3:7.1f} us | step {r['step_ms'] * 1e3:7.1f} us")
                     del P
 
-    def choose(dt):
-        """(height, schedule) of the timed steps: the fastest SpMV of the sweep
-        by the mean of its cold and warm times (the steps run it right after
-        the conversion, between those two conditions), unless --height /
-        --schedule fix them."""
+    def candidates(dt):
+        """(height, schedule) candidates of the timed steps: the three fastest
+        SpMVs of the sweep by the mean of their cold and warm times, unless
+        --height / --schedule fix them."""
         cand = [r for r in sweep if r["dtype"] == dt]
         if args.height and args.schedule:
-            return args.height, args.schedule
+            return [(args.height, args.schedule)]
         pool = [r for r in cand if (not args.height or r["height"] == args.height)
                 and (not args.schedule or r["schedule"] == args.schedule)]
         if pool:
-            best = min(pool, key=lambda r: r["spmv_cold_ms"] + r["spmv_warm_ms"])
-            return best["height"], best["schedule"]
-        return args.height or 32, args.schedule or "colblock4"
+            pool.sort(key=lambda r: r["spmv_cold_ms"] + r["spmv_warm_ms"])
+            return [(r["height"], r["schedule"]) for r in pool[:3]]
+        return [(args.height or 32, args.schedule or "colblock4")]
 
-    # ---------------------------------------------------------------- timed steps
-    def timed_steps(dt):
-        h, sched = choose(dt)
-        P = Pipeline(dt, h, sched)
+    def step_calls(P):
         names = ["from_csr_sorted", "colblock_plan", "spmv", "to_csr"] if P.nb else ["from_csr_sorted", "spmv", "to_csr"]
         calls = [P.convert, P.make_plan, P.spmv, P.back] if P.nb else [P.convert, P.spmv, P.back]
 
@@ -834,6 +831,43 @@ def main():
                 fn()
             if evs is not None:
                 evs[len(calls)].record(stream)
+        return names, calls, step
+
+    selection = {}
+
+    def choose(dt):
+        """The candidate whose SpMV is fastest inside the step (right after the
+        conversion, which neither the cold nor the warm sweep condition is):
+        5 untimed trial steps each; a single candidate is taken as it is."""
+        cands = candidates(dt)
+        if len(cands) == 1:
+            return cands[0]
+        trials = []
+        for h, sched in cands:
+            P = Pipeline(dt, h, sched)
+            names, calls, step = step_calls(P)
+            for _ in range(2):
+                step()
+            evs = [[ev() for _ in range(len(calls) + 1)] for _ in range(5)]
+            for e in evs:
+                step(e)
+            torch.cuda.synchronize()
+            k = names.index("spmv")
+            t = float(np.mean([e[k].elapsed_time(e[k + 1]) for e in evs]))
+            trials.append({"height": h, "schedule": sched, "spmv_in_step_ms": round(t, 5)})
+            del P
+        torch.cuda.empty_cache()
+        selection[dt] = trials
+        best = min(trials, key=lambda r: r["spmv_in_step_ms"])
+        log(f"{dt} choice: " + ", ".join(f"h={r['height']} {r['schedule']} {r['spmv_in_step_ms'] * 1e3:.1f} us"
+                                         for r in trials))
+        return best["height"], best["schedule"]
+
+    # ---------------------------------------------------------------- timed steps
+    def timed_steps(dt):
+        h, sched = choose(dt)
+        P = Pipeline(dt, h, sched)
+        names, calls, step = step_calls(P)
 
         for _ in range(args.warmup):
             step()
@@ -927,7 +961,7 @@ def main():
     }
     detail = dict(res)
     detail.update({"sweep": sweep, "kernel_src": kernel_source_hash(), "step_detail": {"f64": step64, "f32": step32},
-                   "spmv_detail": {"f64": spmv64, "f32": spmv32}})
+                   "spmv_detail": {"f64": spmv64, "f32": spmv32}, "selection_trials": selection})
     path = args.detail or "bench_detail.json"
     try:
         if os.path.dirname(path):
