@@ -419,3 +419,41 @@ def test_to_csr_staged_runs(C, height, dtype):
         M, hv = check_from_csr(C, A, height, sort, dtype)
         rp2, ci2, v2 = check_round_trip(C, A, M, hv)
         assert np.array_equal(rp2.cpu().numpy(), A.row_ptr)
+
+
+def test_graph_replay_sorted_conversion(C):
+    """CSR -> CMRS sorted (short strips in groups, strips listed for one wave,
+    long strips for a workgroup with its shared counter, a strip past the
+    workgroup's LDS) and CMRS -> CSR captured in one HIP graph: its counters
+    are cleared by a kernel, not a memset node.  Every replay, with eager
+    work and the outputs scrambled in between, equals the eager result."""
+    A = _long_strip_matrix(4000, 60000, [5, 6, 1000, 1001, 1002, 3999], 9000, seed=4)
+    h = 8
+    rp, ci, v, hv = G.upload(A)
+    ws = torch.empty(max(1, C.from_csr_workspace_bytes(A.rows, A.nnz, h, True)), dtype=torch.uint8, device="cuda")
+    M = C.from_csr(rp, ci, v, A.cols, h, sort=True, workspace=ws)
+    torch.cuda.synchronize()
+    ref_w, ref_v, ref_sp = M.col_word.clone(), M.val.clone(), M.strip_ptr.clone()
+    back = (torch.empty_like(rp), torch.empty_like(ci), torch.empty_like(v))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            C.from_csr(rp, ci, v, A.cols, h, sort=True, workspace=ws, out=M)
+            C.to_csr(M, out=back)
+    torch.cuda.current_stream().wait_stream(s)
+    for i in range(4):
+        M.col_word.fill_(-1)
+        M.strip_ptr.fill_(-1)
+        M.val.fill_(float("nan"))
+        for t in back:
+            t.fill_(-7)
+        C.from_csr(rp, ci, v, A.cols, 2, sort=True)       # eager work in between
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(M.col_word, ref_w) and torch.equal(M.strip_ptr, ref_sp), f"replay {i}: CMRS"
+        assert np.array_equal(G.val_bits(M.val), G.val_bits(ref_v)), f"replay {i}: values"
+        assert torch.equal(back[0], rp) and torch.equal(back[1], ci), f"replay {i}: CSR"
+        assert np.array_equal(G.val_bits(back[2]), G.val_bits(v)), f"replay {i}: CSR values"
+    check_from_csr(C, A, h, True)
