@@ -412,6 +412,9 @@ __global__ __launch_bounds__(kConvThreads) void from_csr_bucket_kernel(
     int* __restrict__ ws_small, int* __restrict__ ws_big) {
     constexpr int CAP = kWave * E;
     constexpr int NBMAX = CAP / 4;
+    // The bucket count doubles up to NBMAX, so NBMAX must be a power of two
+    // (otherwise it would pass NBMAX and overrun bcnt/bstart).
+    static_assert((NBMAX & (NBMAX - 1)) == 0, "bucket capacity must be a power of two");
     __shared__ uint64_t keys[kConvWaves][CAP];
     __shared__ int bcnt[kConvWaves][NBMAX];
     __shared__ int bstart[kConvWaves][NBMAX];
