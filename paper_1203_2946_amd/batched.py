@@ -19,7 +19,7 @@ from . import cmrs
 
 DEFAULT_CANDIDATES = {
     "tile_nnz": (8_192, 32_768, 131_072),
-    "group": (0, 8),
+    "group": (0, 8, 16),
     "blocks_per_cu": (2, 4, 8),
 }
 

@@ -9,7 +9,10 @@
 // next_pow2(nrhs)) so that the additions of one instruction hit 64 distinct
 // banks.  A strip's results are the sums over its G entry slots; the lane
 // that sums output (s, row, k) starts at slot (row * RB + k) mod G, which
-// spreads the reads of one instruction over distinct banks too.
+// spreads the reads of one instruction over distinct banks too.  From 3
+// right-hand sides on (and for every bucket of the batched kernel) the steps
+// are software-pipelined: each step issues the next step's stream loads
+// before adding its own products (spmm_tile).
 //
 // The batched path runs that body from one persistent kernel: waves take
 // work tiles (a matrix and a range of its strips) from per-XCD queue counters
@@ -30,6 +33,7 @@ namespace cmrs {
 
 constexpr int kSpmmMaxWaves = 4;
 constexpr size_t kSpmmWaveLdsMax = 65536;
+constexpr int kSpmmMaxPassesPerWave = 8;
 
 template <typename T>
 __device__ inline T nt_load(const T* p) {
@@ -41,79 +45,232 @@ __device__ inline bf16_t nt_load(const bf16_t* p) {
     return v;
 }
 
-// Strips [sb, sb + S) (those below s_end) of matrix m; buf holds HB * RB * 64
-// partials of this wave.
 // 16 bytes of X: XV consecutive values of one row.
 template <typename XT>
 struct alignas(16) XVec {
     XT v[16 / sizeof(XT)];
 };
 
-template <int HB, int RB, typename VT, typename XT, typename AT>
-__device__ inline void spmm_pass(const SpmmMat& m, int sb, int s_end, AT* __restrict__ buf, int lane) {
-    constexpr int U = RB >= 4 ? 4 : 8;
+template <int RB>
+struct SpmmUnroll {
+    static constexpr int U = RB >= 4 ? 4 : 8;  // entries per lane in one step
+};
+
+// The stream loads of one step of a lane: the packed words and values of
+// entries base, base + G, ..., base + (U - 1) G of its strip.  Entries past
+// the strip's end are clamped to its last entry, and a lane with no entry at
+// all (past its strip's end, or without a strip) to entry 0, so that every
+// lane loads a valid address with no branch: the compiler then keeps these
+// loads in flight across the gathers and additions that follow them.  Called
+// only for matrices with entries (so entry 0 exists).
+template <int U, typename VT>
+__device__ inline void spmm_load_step(const SpmmMat& m, int base, int G, int hi, uint32_t (&w)[U], VT (&v)[U]) {
+    const VT* __restrict__ val = static_cast<const VT*>(m.val);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int j = max(min(base + u * G, hi - 1), 0);
+        w[u] = nt_load(m.word + j);
+        v[u] = nt_load(val + j);
+    }
+}
+
+// The row pieces x[col][0 .. RB) of the step's U entries, in straight-line
+// code: the first NV 16-byte chunks of each piece as vector loads (the caller
+// picks NV so that they lie below nrhs on 16-byte aligned rows), the rest one
+// value at a time at index min(k, nrhs - 1), a valid address whose value is
+// not used for k >= nrhs.  Entries past the strip's end gather their clamped
+// entry's row and are not added.  With no branch between them, the loads of
+// all U entries are in flight together (a branch per entry made the compiler
+// wait for each entry's gathers before issuing the next ones).
+template <int U, int RB, int NV, typename XT>
+__device__ inline void spmm_gather(const SpmmMat& m, const uint32_t (&w)[U], XT (&xv)[U][RB]) {
     constexpr int XV = static_cast<int>(16 / sizeof(XT));
+    const XT* __restrict__ x = static_cast<const XT*>(m.x);
+    const size_t ldx = static_cast<size_t>(m.ldx);
+    const int last = m.nrhs - 1;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const XT* xr = x + static_cast<size_t>(w[u] >> m.bits) * ldx;
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+            const XVec<XT> t = *reinterpret_cast<const XVec<XT>*>(xr + c * XV);
+#pragma unroll
+            for (int q = 0; q < XV; ++q) xv[u][c * XV + q] = t.v[q];
+        }
+#pragma unroll
+        for (int k = NV * XV; k < RB; ++k) xv[u][k] = xr[min(k, last)];
+    }
+}
+
+// The step's products added to the lane's partials for (row, k), for every
+// entry slot and all RB right-hand-side slots, with no branch: a clamped
+// entry adds +0.0 (its product is replaced, so a non-finite x cannot leak
+// in), and slots k >= nrhs collect products that are never read.  A partial
+// starts at +0.0 and, in round-to-nearest, never becomes -0.0, so adding +0.0
+// leaves it bit for bit unchanged.  (A branch here would let the compiler
+// sink the gathers into it and then wait for every load in flight, the
+// next step's prefetch included, before the first addition.)
+template <int HB, int U, int RB, typename VT, typename XT, typename AT>
+__device__ inline void spmm_accumulate(const SpmmMat& m, int base, int G, int hi, const uint32_t (&w)[U],
+                                       const VT (&v)[U], const XT (&xv)[U][RB], AT* __restrict__ buf, int lane) {
+    const uint32_t mask = (1u << m.bits) - 1u;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const bool ok = base + u * G < hi;
+        const AT a = static_cast<AT>(ValTraits<VT>::widen(v[u]));
+        AT* slot = buf + static_cast<int>(w[u] & mask & (HB - 1)) * RB * kWave + lane;
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+            const AT p = a * static_cast<AT>(xv[u][k]);
+            lds_add(slot + k * kWave, ok ? p : AT(0));
+        }
+    }
+}
+
+// Row sums of the pass over strips [sb, sb + S) (those below s_end), written
+// to Y, and the partials cleared for the next pass.  Output o: strip slot
+// so = o mod S (fastest), partial i = o / S with i = row * RB + k; it sums
+// the G entry slots starting at slot i mod G.
+template <int HB, int RB, typename XT, typename AT>
+__device__ inline void spmm_finish(const SpmmMat& m, int sb, int s_end, AT* __restrict__ buf, int lane) {
     constexpr int SLOTS = HB * RB;
     const int g_log = m.g_log;
     const int G = 1 << g_log;
     const int s_log = 6 - g_log;
-    const int e = lane & (G - 1);
-    const int s = sb + (lane >> g_log);
-    const int bits = m.bits;
-    const int nrhs = m.nrhs;
-    const uint32_t mask = (1u << bits) - 1u;
+    const int nout = SLOTS << s_log;
+    XT* __restrict__ y = static_cast<XT*>(m.y);
+    const size_t ldy = static_cast<size_t>(m.ldy);
+    wave_lds_sync();
+    for (int o = lane; o < nout; o += kWave) {
+        const int so = o & ((1 << s_log) - 1);
+        const int i = o >> s_log;
+        const int k = i & (RB - 1);
+        const int rr = i / RB;
+        const AT* p = buf + i * kWave + (so << g_log);
+        AT sum = AT(0);
+        // Eight reads in flight at a time, added in the same order.
+        int q = 0;
+        for (; q + 8 <= G; q += 8) {
+            AT t[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) t[j] = p[(q + j + i) & (G - 1)];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) sum += t[j];
+        }
+        for (; q < G; ++q) sum += p[(q + i) & (G - 1)];
+        const int strip = sb + so;
+        const long long row = static_cast<long long>(strip) * m.height + rr;
+        if (strip < s_end && rr < m.height && row < m.rows && k < m.nrhs)
+            y[static_cast<size_t>(row) * ldy + k] = static_cast<XT>(sum);
+    }
+    wave_lds_sync();
 #pragma unroll
     for (int i = 0; i < SLOTS; ++i) buf[i * kWave + lane] = AT(0);
+}
+
+// Strips [s0, s1) of matrix m in passes of S = 64 / G strips; buf holds the
+// HB * RB * 64 partials of this wave.  Lane (s, e) walks entries e, e + G, ...
+// of its strip, U per step.  The loads are software-pipelined: a step first
+// gathers its X pieces, then issues the stream loads of the next step (of
+// this pass, or the first of the next pass, whose strip pointers were read one
+// pass ahead), and only then adds its products, so the next step's HBM
+// latency overlaps this step's gathers, additions and the pass-end reduction.
+// Every load of the step is issued by every lane at a valid address (clamped
+// entries and strip indices), with no branch around it: at a branch the
+// compiler would have to assume the worst of the loads still in flight and
+// wait for the prefetch too.  The additions per lane and the reduction run in
+// the same order as without the pipelining.
+template <int HB, int RB, int NV, typename VT, typename XT, typename AT>
+__device__ inline void spmm_tile(const SpmmMat& m, int s0, int s1, AT* __restrict__ buf, int lane) {
+    constexpr int U = SpmmUnroll<RB>::U;
+    constexpr int SLOTS = HB * RB;
+    const int g_log = m.g_log;
+    const int G = 1 << g_log;
+    const int S = kWave >> g_log;
+    const int e = lane & (G - 1);
+    const int32_t* __restrict__ sp = m.strip_ptr;
+#pragma unroll
+    for (int i = 0; i < SLOTS; ++i) buf[i * kWave + lane] = AT(0);
+    if (m.nnz == 0) {
+        // No entries to load: every row sum is zero.
+        for (int sb = s0; sb < s1; sb += S) spmm_finish<HB, RB, XT, AT>(m, sb, s1, buf, lane);
+        return;
+    }
+    // A lane whose strip is at or past s1 gets the empty range [sp[s1], sp[s1]).
+    int s = s0 + (lane >> g_log);
+    int lo = sp[min(s, s1)], hi = sp[min(s + 1, s1)];
+    int lo_n = sp[min(s + S, s1)], hi_n = sp[min(s + S + 1, s1)];
+    int base = lo + e;
+    uint32_t w[U];
+    VT v[U];
+    spmm_load_step<U, VT>(m, base, G, hi, w, v);
+    for (int sb = s0;;) {
+        XT xv[U][RB];
+        spmm_gather<U, RB, NV, XT>(m, w, xv);
+        const int nb = base + U * G;
+        const bool more = ballot(nb < hi) != 0ull;
+        uint32_t w2[U];
+        VT v2[U];
+        spmm_load_step<U, VT>(m, more ? nb : lo_n + e, G, more ? hi : hi_n, w2, v2);
+        spmm_accumulate<HB, U, RB, VT, XT, AT>(m, base, G, hi, w, v, xv, buf, lane);
+        if (more) {
+            base = nb;
+        } else {
+            spmm_finish<HB, RB, XT, AT>(m, sb, s1, buf, lane);
+            sb += S;
+            if (sb >= s1) break;
+            s += S;
+            lo = lo_n;
+            hi = hi_n;
+            base = lo + e;
+            lo_n = sp[min(s + S, s1)];
+            hi_n = sp[min(s + S + 1, s1)];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            w[u] = w2[u];
+            v[u] = v2[u];
+        }
+    }
+}
+
+// One pass over strips [sb, sb + S) (those below s_end) for one or two
+// right-hand sides, without the pipelining: a lane loads the words and values
+// of its U entries, gathers and adds only those inside its strip (branches
+// that skip the additions of entries past the end).  As a single launch with
+// one pass per wave this is faster than the branch-free pipelined step, which
+// adds +0.0 for every clamped entry (measured 11-16 % on 2*10^6-row band and
+// stencil matrices).  It sums the same products in the same order.
+template <int HB, int RB, typename VT, typename XT, typename AT>
+__device__ inline void spmm_pass_small(const SpmmMat& m, int sb, int s_end, AT* __restrict__ buf, int lane) {
+    static_assert(RB <= 2, "one or two right-hand-side slots");
+    constexpr int U = SpmmUnroll<RB>::U;
+    const int g_log = m.g_log;
+    const int G = 1 << g_log;
+    const int e = lane & (G - 1);
+    const int s = sb + (lane >> g_log);
+    const uint32_t mask = (1u << m.bits) - 1u;
     if (s < s_end) {
         const int lo = m.strip_ptr[s], hi = m.strip_ptr[s + 1];
         const VT* __restrict__ val = static_cast<const VT*>(m.val);
         const XT* __restrict__ x = static_cast<const XT*>(m.x);
         const size_t ldx = static_cast<size_t>(m.ldx);
         for (int base = lo + e; base < hi; base += U * G) {
-            // Out-of-range entries are clamped to the last one of the strip
-            // (a valid address), so the stream loads of the step issue
-            // without a branch; their gathers are masked off.
             uint32_t w[U];
             VT v[U];
-            XT xv[U][RB];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int j = min(base + u * G, hi - 1);
                 w[u] = nt_load(m.word + j);
                 v[u] = nt_load(val + j);
             }
-            // The row piece x[col][0 .. nrhs) of every entry: 16-byte loads
-            // where X keeps its rows aligned, single loads otherwise, the slots
-            // past nrhs not loaded (nrhs is the same in every lane).  fp64 X
-            // with fewer than 4 right-hand-side slots: one load per slot, the
-            // slots past nrhs reading x_0 (measured faster there; from 4 slots
-            // on the 16-byte loads are faster, e.g. 481 -> 363 us for 8
-            // right-hand sides on a 27-point stencil of 2*10^6 rows).
+            XT xv[U][RB];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (base + u * G < hi) {
-                    const XT* xr = x + static_cast<size_t>(w[u] >> bits) * ldx;
-                    if constexpr (sizeof(XT) == 8 && RB < 4) {
+                    const XT* xr = x + static_cast<size_t>(w[u] >> m.bits) * ldx;
 #pragma unroll
-                        for (int k = 0; k < RB; ++k) xv[u][k] = xr[k < nrhs ? k : 0];
-                    } else if (RB >= XV && m.xvec) {
-#pragma unroll
-                        for (int k = 0; k < RB; k += XV) {
-                            if (k + XV <= nrhs) {
-                                const XVec<XT> t = *reinterpret_cast<const XVec<XT>*>(xr + k);
-#pragma unroll
-                                for (int q = 0; q < XV; ++q) xv[u][k + q] = t.v[q];
-                            } else {
-#pragma unroll
-                                for (int q = 0; q < XV; ++q)
-                                    if (k + q < nrhs) xv[u][k + q] = xr[k + q];
-                            }
-                        }
-                    } else {
-#pragma unroll
-                        for (int k = 0; k < RB; ++k)
-                            if (k < nrhs) xv[u][k] = xr[k];
-                    }
+                    for (int k = 0; k < RB; ++k) xv[u][k] = xr[k];
                 }
             }
 #pragma unroll
@@ -122,62 +279,74 @@ __device__ inline void spmm_pass(const SpmmMat& m, int sb, int s_end, AT* __rest
                     const AT a = static_cast<AT>(ValTraits<VT>::widen(v[u]));
                     AT* slot = buf + static_cast<int>(w[u] & mask & (HB - 1)) * RB * kWave + lane;
 #pragma unroll
-                    for (int k = 0; k < RB; ++k)
-                        if (k < nrhs) lds_add(slot + k * kWave, a * static_cast<AT>(xv[u][k]));
+                    for (int k = 0; k < RB; ++k) lds_add(slot + k * kWave, a * static_cast<AT>(xv[u][k]));
                 }
             }
         }
     }
-    wave_lds_sync();
-    // Output o: strip slot so = o mod S (fastest), partial i = o / S with
-    // i = row * RB + k; it sums the G entry slots starting at slot i mod G.
-    constexpr int NOUT_PER_S = SLOTS;
-    const int nout = NOUT_PER_S << s_log;
-    XT* __restrict__ y = static_cast<XT*>(m.y);
-    const size_t ldy = static_cast<size_t>(m.ldy);
-    for (int o = lane; o < nout; o += kWave) {
-        const int so = o & ((1 << s_log) - 1);
-        const int i = o >> s_log;
-        const int k = i & (RB - 1);
-        const int rr = i / RB;
-        const AT* p = buf + i * kWave + (so << g_log);
-        AT sum = AT(0);
-        for (int q = 0; q < G; ++q) sum += p[(q + i) & (G - 1)];
-        const int strip = sb + so;
-        const long long row = static_cast<long long>(strip) * m.height + rr;
-        if (strip < s_end && rr < m.height && row < m.rows && k < nrhs)
-            y[static_cast<size_t>(row) * ldy + k] = static_cast<XT>(sum);
-    }
-    wave_lds_sync();
+    spmm_finish<HB, RB, XT, AT>(m, sb, s_end, buf, lane);
 }
 
+// How many 16-byte chunks of each X piece are read as vector loads: all of
+// them when X keeps its rows 16-byte aligned and nrhs fills the bucket, the
+// ones below RB / 2 (always below nrhs, as RB = next_pow2(nrhs)) when it does
+// not, none for unaligned X.  fp64 pieces of fewer than 4 slots are read one
+// value at a time (measured faster there).
+// Buckets whose partials exceed a wave's LDS share are never planned
+// (spmm_fits) and not compiled.
 template <int HB, int RB, typename VT, typename XT, typename AT>
-__global__ __launch_bounds__(kSpmmMaxWaves * kWave) void spmm_kernel(SpmmMat m, int strips) {
+__device__ inline void spmm_tile_nv(const SpmmMat& m, int s0, int s1, AT* buf, int lane) {
+    constexpr int XV = static_cast<int>(16 / sizeof(XT));
+    constexpr bool VEC = RB >= XV && !(sizeof(XT) == 8 && RB < 4);
+    if constexpr (static_cast<size_t>(HB) * RB * kWave * sizeof(AT) > kSpmmWaveLdsMax) {
+        return;
+    } else if constexpr (!VEC) {
+        spmm_tile<HB, RB, 0, VT, XT, AT>(m, s0, s1, buf, lane);
+    } else {
+        if (!m.xvec)
+            spmm_tile<HB, RB, 0, VT, XT, AT>(m, s0, s1, buf, lane);
+        else if (m.nrhs == RB)
+            spmm_tile<HB, RB, RB / XV, VT, XT, AT>(m, s0, s1, buf, lane);
+        else
+            spmm_tile<HB, RB, RB / 2 / XV, VT, XT, AT>(m, s0, s1, buf, lane);
+    }
+}
+
+// One launch over one matrix: wave w takes the `passes` consecutive passes
+// of strips [w * passes * S, (w + 1) * passes * S), so the next pass's loads
+// overlap the current one's work as in the batched kernel.  One or two
+// right-hand sides: one pass per wave through spmm_pass_small, measured
+// faster there as a single launch (the batched kernel runs those buckets
+// through the pipelined loop too, where that was faster).
+template <int HB, int RB, typename VT, typename XT, typename AT>
+__global__ __launch_bounds__(kSpmmMaxWaves * kWave) void spmm_kernel(SpmmMat m, int strips, int passes) {
     extern __shared__ __align__(16) unsigned char spmm_lds[];
     AT* buf = reinterpret_cast<AT*>(spmm_lds);
     const int lane = lane_id();
     const int wpb = static_cast<int>(blockDim.x) / kWave;
     const int wave = uniform(static_cast<int>(threadIdx.x) / kWave);
-    const int s_log = 6 - m.g_log;
-    const long long sb =
-        (static_cast<long long>(xcd_logical_block(blockIdx.x, gridDim.x)) * wpb + wave) << s_log;
+    const long long span = static_cast<long long>(passes) << (6 - m.g_log);
+    const long long sb = (static_cast<long long>(xcd_logical_block(blockIdx.x, gridDim.x)) * wpb + wave) * span;
     if (sb >= strips) return;
-    spmm_pass<HB, RB, VT, XT, AT>(m, static_cast<int>(sb), strips, buf + wave * (HB * RB * kWave), lane);
-}
-
-template <int HB, int RB, typename VT, typename XT, typename AT>
-__device__ inline void spmm_tile(const SpmmMat& m, int s0, int s1, AT* buf, int lane) {
-    const int S = kWave >> m.g_log;
-    for (int sb = s0; sb < s1; sb += S) spmm_pass<HB, RB, VT, XT, AT>(m, sb, s1, buf, lane);
+    const int s1 = static_cast<int>(std::min<long long>(strips, sb + span));
+    buf += wave * (HB * RB * kWave);
+    if constexpr (RB <= 2) {
+        // One pass per wave (passes == 1), no pipelining.
+#pragma unroll
+        for (int i = 0; i < HB * RB; ++i) buf[i * kWave + lane] = AT(0);
+        spmm_pass_small<HB, RB, VT, XT, AT>(m, static_cast<int>(sb), s1, buf, lane);
+    } else {
+        spmm_tile_nv<HB, RB, VT, XT, AT>(m, static_cast<int>(sb), s1, buf, lane);
+    }
 }
 
 template <int HB, typename VT, typename XT, typename AT>
 __device__ inline void spmm_tile_rb(const SpmmMat& m, int s0, int s1, AT* buf, int lane) {
     switch (m.rb_log) {
-        case 0: spmm_tile<HB, 1, VT, XT, AT>(m, s0, s1, buf, lane); break;
-        case 1: spmm_tile<HB, 2, VT, XT, AT>(m, s0, s1, buf, lane); break;
-        case 2: spmm_tile<HB, 4, VT, XT, AT>(m, s0, s1, buf, lane); break;
-        default: spmm_tile<HB, 8, VT, XT, AT>(m, s0, s1, buf, lane); break;
+        case 0: spmm_tile_nv<HB, 1, VT, XT, AT>(m, s0, s1, buf, lane); break;
+        case 1: spmm_tile_nv<HB, 2, VT, XT, AT>(m, s0, s1, buf, lane); break;
+        case 2: spmm_tile_nv<HB, 4, VT, XT, AT>(m, s0, s1, buf, lane); break;
+        default: spmm_tile_nv<HB, 8, VT, XT, AT>(m, s0, s1, buf, lane); break;
     }
 }
 
@@ -191,7 +360,7 @@ constexpr int kQueueStride = 16;
 constexpr int kQueueDone = kNumXcd * kQueueStride;
 
 template <typename VT, typename XT, typename AT>
-__global__ __launch_bounds__(kSpmmMaxWaves * kWave) __attribute__((amdgpu_waves_per_eu(4))) void spmm_persistent_kernel(
+__global__ __launch_bounds__(kSpmmMaxWaves * kWave) void spmm_persistent_kernel(
     const SpmmMat* __restrict__ mats, const SpmmTile* __restrict__ tiles, int ntiles, unsigned* __restrict__ queue,
     int waves_total, int wave_slots) {
     extern __shared__ __align__(16) unsigned char spmm_lds[];
@@ -250,9 +419,15 @@ int ilog2(int v) {
 template <int HB, int RB, typename VT, typename XT, typename AT>
 void launch_spmm_hb_rb(const SpmmMat& m, int strips, int wpb, size_t lds, hipStream_t stream) {
     const int S = kWave >> m.g_log;
-    const long long waves = (static_cast<long long>(strips) + S - 1) / S;
+    const long long npass = (static_cast<long long>(strips) + S - 1) / S;
+    // Several passes per wave once there are enough waves to fill the chip
+    // twice over (256 CUs x 16 resident waves).
+    int passes = 1;
+    while (RB > 2 && passes < kSpmmMaxPassesPerWave && npass >= 2LL * passes * 8192) passes *= 2;
+    const long long waves = (npass + passes - 1) / passes;
     const int grid = static_cast<int>((waves + wpb - 1) / wpb);
-    hipLaunchKernelGGL((spmm_kernel<HB, RB, VT, XT, AT>), dim3(grid), dim3(wpb * kWave), lds, stream, m, strips);
+    hipLaunchKernelGGL((spmm_kernel<HB, RB, VT, XT, AT>), dim3(grid), dim3(wpb * kWave), lds, stream, m, strips,
+                       passes);
 }
 
 template <int HB, typename VT, typename XT, typename AT>
@@ -309,17 +484,25 @@ SpmmMat spmm_mat(const cmrs_mat_t* A, int nrhs, const void* X, int ldx, void* Y,
     m.height = A->height;
     m.bits = A->bits;
     m.nrhs = nrhs;
+    m.nnz = A->nnz;
     m.ldx = ldx;
     m.ldy = ldy;
     m.hb = next_pow2(A->height);
     m.rb_log = ilog2(nrhs);
     int g = group;
     if (g <= 0) {
-        // Enough entry slots that one unrolled step covers the mean strip.
+        // Enough entry slots that one unrolled step covers the mean strip,
+        // but at most 128 / RB for 4 or more right-hand-side slots: a pass
+        // then takes several steps, which spreads its reduction (64 * HB *
+        // RB partials whatever G is) over more entries and gives the
+        // prefetch of the next step something to overlap (measured on band
+        // and stencil matrices of 2*10^6 rows, height 2 and 4: e.g. 1146 ->
+        // 574 us for 8 right-hand sides, fp64, height 4).
         const int unroll = (1 << m.rb_log) >= 4 ? 4 : 8;
         const int strips = (A->rows + A->height - 1) / A->height;
         const double mean = strips > 0 ? static_cast<double>(A->nnz) / strips : 0.0;
-        g = next_pow2(static_cast<int>(std::min(64.0, std::max(1.0, mean / unroll))));
+        const double cap = m.rb_log >= 2 ? 128.0 / (1 << m.rb_log) : 64.0;
+        g = next_pow2(static_cast<int>(std::min(cap, std::max(1.0, mean / unroll))));
     }
     if (g > kWave) g = kWave;
     m.g_log = ilog2(g);

@@ -122,6 +122,33 @@ def test_spmm_groups_and_padded_blocks(C, group):
     assert np.array_equal(Y2.cpu().numpy().view(np.uint64), full[:, :nrhs].copy().view(np.uint64))
 
 
+@pytest.mark.parametrize("dtype,group,nrhs,ld", [("f64", 64, 8, 8), ("f64", 16, 5, 6), ("f64", 16, 4, 4),
+                                                  ("f64", 16, 7, 7), ("f32", 16, 7, 8), ("f32", 64, 3, 4)])
+def test_spmm_several_passes_per_wave(C, dtype, group, nrhs, ld):
+    """A single launch large enough that each wave takes 2-8 consecutive
+    passes (the pipelined loop: the next step's loads are issued before this
+    step's additions, clamped at strip and tile ends).  X rows 16-byte
+    aligned with nrhs below the bucket (vector loads for the lower half of the
+    bucket, single loads above), and unaligned ones.  Columns within the
+    bounds; the persistent batched launch of the same matrix and group gives
+    the same bits."""
+    A = synth.poisson_rows(400_000, 6.0, seed=nrhs + group)
+    rp, ci, v, hv = G.upload(A, dtype)
+    M = C.from_csr(rp, ci, v, A.cols, 2, sort=True)
+    X, Xs = _rhs(A, nrhs, dtype, seed=nrhs, ld=ld)
+    Y = C.spmm(M, X, group=group)
+    torch.cuda.synchronize()
+    y = Y.cpu().numpy().astype(np.float64)
+    _check_cols(A, hv, dtype, Xs, y)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    Yb = torch.full((A.rows, nrhs), float("nan"), dtype=tdt, device="cuda")
+    plan = C.spmm_plan([M], [X], [Yb], tile_nnz=200_000, group=group)
+    C.spmm_batched(plan)
+    torch.cuda.synchronize()
+    ut = np.uint64 if dtype == "f64" else np.uint32
+    assert np.array_equal(Yb.cpu().numpy().view(ut), Y.cpu().numpy().view(ut))
+
+
 def test_spmm_no_entries(C):
     A = synth.random_csr(777, 300, max_row=0, seed=1)
     assert A.nnz == 0
