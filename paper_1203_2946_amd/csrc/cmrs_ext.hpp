@@ -20,7 +20,7 @@ struct alignas(16) SpmmMat {
     int32_t rows, height, bits, nrhs;
     int32_t ldx, ldy, hb, rb_log;     // hb = next_pow2(height), 2^rb_log = next_pow2(nrhs)
     int32_t g_log;                    // 2^g_log entry slots per strip
-    int32_t xvec;                     // 1: X and ldx keep every X row 16-byte aligned
+    int32_t pad0;
     int32_t nnz;                      // stored entries (strip_ptr[strips])
     int32_t pad;
 };

@@ -45,12 +45,6 @@ __device__ inline bf16_t nt_load(const bf16_t* p) {
     return v;
 }
 
-// 16 bytes of X: XV consecutive values of one row.
-template <typename XT>
-struct alignas(16) XVec {
-    XT v[16 / sizeof(XT)];
-};
-
 template <int RB>
 struct SpmmUnroll {
     static constexpr int U = RB >= 4 ? 4 : 8;  // entries per lane in one step
@@ -82,20 +76,67 @@ __device__ inline void spmm_load_step(const SpmmMat& m, int base, int G, int hi,
 // entry's row and are not added.  With no branch between them, the loads of
 // all U entries are in flight together (a branch per entry made the compiler
 // wait for each entry's gathers before issuing the next ones).
+// 16 bytes of X: XV consecutive values of one row, at an element boundary
+// (dword alignment is all the load needs).
+template <typename XT>
+struct XLoose;
+template <>
+struct XLoose<double> {
+    typedef double type __attribute__((ext_vector_type(2), aligned(8)));
+};
+template <>
+struct XLoose<float> {
+    typedef float type __attribute__((ext_vector_type(4), aligned(4)));
+};
+
 template <int U, int RB, int NV, typename XT>
 __device__ inline void spmm_gather(const SpmmMat& m, const uint32_t (&w)[U], XT (&xv)[U][RB]) {
     constexpr int XV = static_cast<int>(16 / sizeof(XT));
     const XT* __restrict__ x = static_cast<const XT*>(m.x);
     const size_t ldx = static_cast<size_t>(m.ldx);
     const int last = m.nrhs - 1;
+    if constexpr (NV < 0) {
+        // nrhs between RB/2 and RB, nrhs >= XV: every chunk as one 16-byte
+        // load; the chunks below RB/2 lie below nrhs,
+        // the others are moved back to end at nrhs (overlapping the chunk
+        // before), and slot k takes element k - start of its chunk (slots
+        // k >= nrhs take any element: their products are never read).
+        // 4 loads per entry instead of 6 for 5-7 right-hand sides in fp64,
+        // 2 instead of 5 in fp32.
+        typedef typename XLoose<XT>::type XL;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const XT* xr = x + static_cast<size_t>(w[u] >> m.bits) * ldx;
+#pragma unroll
+            for (int c = 0; c < RB / XV; ++c) {
+                if (c * XV + XV <= RB / 2) {
+                    const XL t = *reinterpret_cast<const XL*>(xr + c * XV);
+#pragma unroll
+                    for (int q = 0; q < XV; ++q) xv[u][c * XV + q] = t[q];
+                } else {
+                    const int st = min(c * XV, m.nrhs - XV);
+                    const XL t = *reinterpret_cast<const XL*>(xr + st);
+#pragma unroll
+                    for (int q = 0; q < XV; ++q) {
+                        const int p = min(c * XV + q - st, XV - 1);
+                        XT vq = t[XV - 1];
+#pragma unroll
+                        for (int r = XV - 2; r >= 0; --r) vq = p == r ? t[r] : vq;
+                        xv[u][c * XV + q] = vq;
+                    }
+                }
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const XT* xr = x + static_cast<size_t>(w[u] >> m.bits) * ldx;
 #pragma unroll
         for (int c = 0; c < NV; ++c) {
-            const XVec<XT> t = *reinterpret_cast<const XVec<XT>*>(xr + c * XV);
+            const typename XLoose<XT>::type t = *reinterpret_cast<const typename XLoose<XT>::type*>(xr + c * XV);
 #pragma unroll
-            for (int q = 0; q < XV; ++q) xv[u][c * XV + q] = t.v[q];
+            for (int q = 0; q < XV; ++q) xv[u][c * XV + q] = t[q];
         }
 #pragma unroll
         for (int k = NV * XV; k < RB; ++k) xv[u][k] = xr[min(k, last)];
@@ -288,10 +329,13 @@ __device__ inline void spmm_pass_small(const SpmmMat& m, int sb, int s_end, AT* 
 }
 
 // How many 16-byte chunks of each X piece are read as vector loads: all of
-// them when X keeps its rows 16-byte aligned and nrhs fills the bucket, the
-// ones below RB / 2 (always below nrhs, as RB = next_pow2(nrhs)) when it does
-// not, none for unaligned X.  fp64 pieces of fewer than 4 slots are read one
-// value at a time (measured faster there).
+// them (those reaching past nrhs moved back to end at nrhs, NV = -1, when
+// nrhs does not fill the bucket; at least one chunk's worth of right-hand
+// sides needed).  The loads need the elements' own alignment only (dword
+// alignment is what a 16-byte global load requires), so any leading
+// dimension takes them: with rows of 5 or 7 doubles (or 3, 5, 6, 7 floats) a
+// piece costs 4 (2) loads instead of 6 (5).  fp64 pieces of fewer than 4
+// slots are read one value at a time (measured faster there).
 // Buckets whose partials exceed a wave's LDS share are never planned
 // (spmm_fits) and not compiled.
 template <int HB, int RB, typename VT, typename XT, typename AT>
@@ -303,12 +347,12 @@ __device__ inline void spmm_tile_nv(const SpmmMat& m, int s0, int s1, AT* buf, i
     } else if constexpr (!VEC) {
         spmm_tile<HB, RB, 0, VT, XT, AT>(m, s0, s1, buf, lane);
     } else {
-        if (!m.xvec)
-            spmm_tile<HB, RB, 0, VT, XT, AT>(m, s0, s1, buf, lane);
-        else if (m.nrhs == RB)
+        if (m.nrhs == RB)
             spmm_tile<HB, RB, RB / XV, VT, XT, AT>(m, s0, s1, buf, lane);
+        else if (m.nrhs >= XV)
+            spmm_tile<HB, RB, -1, VT, XT, AT>(m, s0, s1, buf, lane);
         else
-            spmm_tile<HB, RB, RB / 2 / XV, VT, XT, AT>(m, s0, s1, buf, lane);
+            spmm_tile<HB, RB, 0, VT, XT, AT>(m, s0, s1, buf, lane);
     }
 }
 
@@ -360,7 +404,7 @@ constexpr int kQueueStride = 16;
 constexpr int kQueueDone = kNumXcd * kQueueStride;
 
 template <typename VT, typename XT, typename AT>
-__global__ __launch_bounds__(kSpmmMaxWaves * kWave) void spmm_persistent_kernel(
+__global__ __launch_bounds__(kSpmmMaxWaves * kWave) __attribute__((amdgpu_waves_per_eu(sizeof(AT) == 8 ? 4 : 1))) void spmm_persistent_kernel(
     const SpmmMat* __restrict__ mats, const SpmmTile* __restrict__ tiles, int ntiles, unsigned* __restrict__ queue,
     int waves_total, int wave_slots) {
     extern __shared__ __align__(16) unsigned char spmm_lds[];
@@ -506,8 +550,6 @@ SpmmMat spmm_mat(const cmrs_mat_t* A, int nrhs, const void* X, int ldx, void* Y,
     }
     if (g > kWave) g = kWave;
     m.g_log = ilog2(g);
-    const size_t xs = A->val_dtype == CMRS_R64F ? 8 : 4;  // X holds doubles with fp64 values, else floats
-    m.xvec = (reinterpret_cast<uintptr_t>(X) % 16 == 0 && (static_cast<size_t>(ldx) * xs) % 16 == 0) ? 1 : 0;
     return m;
 }
 
