@@ -97,12 +97,12 @@ __device__ inline void spmm_gather(const SpmmMat& m, const uint32_t (&w)[U], XT 
     const int last = m.nrhs - 1;
     if constexpr (NV < 0) {
         // nrhs between RB/2 and RB, nrhs >= XV: every chunk as one 16-byte
-        // load; the chunks below RB/2 lie below nrhs,
-        // the others are moved back to end at nrhs (overlapping the chunk
-        // before), and slot k takes element k - start of its chunk (slots
-        // k >= nrhs take any element: their products are never read).
-        // 4 loads per entry instead of 6 for 5-7 right-hand sides in fp64,
-        // 2 instead of 5 in fp32.
+        // load; the chunks below RB/2 lie below nrhs, the others are moved
+        // back to end at nrhs (overlapping the chunk before), and slot k takes
+        // element k - start of its chunk (slots k >= nrhs take any element:
+        // their products are never read).  For 5-7 right-hand sides that is
+        // 4 loads per entry in fp64 and 2 in fp32, against up to 8 single
+        // loads.
         typedef typename XLoose<XT>::type XL;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
