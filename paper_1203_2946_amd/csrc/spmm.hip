@@ -18,9 +18,8 @@
 // work tiles (a matrix and a range of its strips) from per-XCD queue counters
 // in the plan until every queue is empty; the last wave out resets the
 // counters, so the same plan can be launched again and replayed from a HIP
-// graph.  A grid
-// stride over strip passes (the listing's loop over strips in the paper's
-// appendix) is the special case of one tile per wave.
+// graph.  A grid stride over strip passes (the listing's loop over strips in
+// the paper's appendix) is the special case of one tile per wave.
 #include <string.h>
 
 #include <algorithm>
