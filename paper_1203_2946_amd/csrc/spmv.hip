@@ -216,7 +216,12 @@ hipError_t launch_one(const Launch& L) {
 template <typename VT, typename XT, typename AT, int HB, int G, bool NT>
 hipError_t launch_group_g(const Launch& L) {
     constexpr int NG = kWave / G;
-    constexpr int U = 8;
+    // Loads per lane in one step: 1.5 times the entries a lane gets from
+    // spmv_group_width (4 up to height 8, so 6; 8 above it, kept at 8: 12
+    // would cost registers).  Cold, 2^20 Poisson(16) rows, fp32: height 2/4
+    // 179/155 -> 164/146 us against 8; the skewed rows unchanged to height 8,
+    // 162 -> 173 us at height 32 with 6.
+    constexpr int U = HB <= 8 ? 6 : 8;
     const int waves = (L.strips + NG - 1) / NG;
     const int blocks = (waves + kSpmvWaves - 1) / kSpmvWaves;
     hipLaunchKernelGGL((spmv_group_kernel<HB, G, U, NT, VT, XT, AT>), dim3(blocks), dim3(kSpmvThreads), 0, L.stream,
@@ -249,7 +254,12 @@ hipError_t launch_group(const Launch& L) {
 template <typename VT, typename XT, typename AT, int HB, int G>
 hipError_t launch_concurrent_g(const Launch& L) {
     constexpr int NG = kWave / G;
-    constexpr int U = 8;
+    // Loads per lane in one step: 1.5 times the ~4 entries a lane gets (the
+    // rule below), so nearly every run takes one step while few loads go to
+    // the clamped slots past its end (cold, 2^20 Poisson(16) rows, 4 blocks,
+    // height 32: fp64 136 -> 130 us, fp32 116 -> 109 us against 8; 4 was
+    // slower, 160 us).
+    constexpr int U = 6;
     const int waves = (L.strips + NG - 1) / NG;
     const int blocks_per_cb = (waves + kSpmvWaves - 1) / kSpmvWaves;
     auto* part = static_cast<AT*>(L.partial);
