@@ -216,12 +216,14 @@ hipError_t launch_one(const Launch& L) {
 template <typename VT, typename XT, typename AT, int HB, int G, bool NT>
 hipError_t launch_group_g(const Launch& L) {
     constexpr int NG = kWave / G;
-    // Loads per lane in one step: 1.5 times the entries a lane gets from
-    // spmv_group_width (4 up to height 8, so 6; 8 above it, kept at 8: 12
-    // would cost registers).  Cold, 2^20 Poisson(16) rows, fp32: height 2/4
-    // 179/155 -> 164/146 us against 8; the skewed rows unchanged to height 8,
-    // 162 -> 173 us at height 32 with 6.
-    constexpr int U = HB <= 8 ? 6 : 8;
+    // Loads per lane in one step: about 1.5 times the entries a lane gets
+    // from spmv_group_width (4 up to height 8, 8 above), so that most strips
+    // take one step while few loads go to the clamped slots past their end:
+    // 6 up to height 8, 12 at height 32; 8 at height 16, where 12 was mixed.
+    // Cold, against 8 everywhere: 2^20 Poisson(16) rows, fp32, height
+    // 2/4/32 179/155/125 -> 164/146/112 us; the skewed rows, fp64, height 32
+    // 162 -> 154 us (6 there: 173 us).
+    constexpr int U = HB <= 8 ? 6 : (HB <= 16 ? 8 : 12);
     const int waves = (L.strips + NG - 1) / NG;
     const int blocks = (waves + kSpmvWaves - 1) / kSpmvWaves;
     hipLaunchKernelGGL((spmv_group_kernel<HB, G, U, NT, VT, XT, AT>), dim3(blocks), dim3(kSpmvThreads), 0, L.stream,

@@ -271,7 +271,11 @@ hipError_t launch_split_g(const cmrs_mat_t* A, const SplitShape& s, const void* 
     }
     const char* base = static_cast<const char*>(buf);
     char* mbase = const_cast<char*>(base);
-    hipLaunchKernelGGL((spmv_split_kernel<HB, G, kSplitU, true, VT, XT, AT>), dim3(chunk_blocks + group_blocks),
+    // 6 loads per lane in a step up to height 8 (1.5 times the 4 entries a
+    // lane gets there; skewed rows, cold, h = 8: fp64 139 -> 134 us, fp32
+    // 103 -> 98 us), kSplitU above (12 was slower at h = 16: 124 -> 131 us).
+    constexpr int SU = HB <= 8 ? 6 : kSplitU;
+    hipLaunchKernelGGL((spmv_split_kernel<HB, G, SU, true, VT, XT, AT>), dim3(chunk_blocks + group_blocks),
                        dim3(kSpmvThreads), 0, stream, A->rows, strips, A->height, A->bits, A->strip_ptr, A->col_word,
                        static_cast<const VT*>(A->val), static_cast<const XT*>(x), static_cast<XT*>(y), s.long_len,
                        chunk_blocks, s.max_chunks, reinterpret_cast<const int*>(base),
