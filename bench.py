@@ -69,7 +69,7 @@ def parse():
     p.add_argument("--rows", type=int, default=1 << 20)
     p.add_argument("--no-extras", action="store_true",
                    help="skip the selector, batched, precision and padded reports")
-    p.add_argument("--only", choices=["batched", "precision", "structured", "residual", "padded_small_mu"],
+    p.add_argument("--only", choices=["batched", "precision", "structured", "residual", "padded_small_mu", "selector"],
                    default=None,
                    help="run only that report (for profiling) and print it as one JSON line")
     p.add_argument("--batched-fixed", default=None,
@@ -660,6 +660,16 @@ def padded_small_mu_report():
     return out
 
 
+def _selector_on_benchmark_matrix(rows: int):
+    """The selector report on the benchmark matrix alone (for profiling)."""
+    import torch
+    import synth
+    A = synth.poisson_rows(rows, 16.0, seed=0)
+    dev = torch.device("cuda:0")
+    return selector_report(torch.from_numpy(A.row_ptr).to(dev), torch.from_numpy(A.col_ind).to(dev),
+                           torch.from_numpy(A.val).to(dev), A.cols)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -686,7 +696,8 @@ def main():
     if args.only:
         rep = {"batched": lambda: batched_report(args.batched_fixed), "precision": precision_report,
                "structured": structured_report, "residual": residual_report,
-               "padded_small_mu": padded_small_mu_report}[args.only]()
+               "padded_small_mu": padded_small_mu_report,
+               "selector": lambda: _selector_on_benchmark_matrix(args.rows)}[args.only]()
         print(json.dumps({args.only: rep}), flush=True)
         return
     dev = torch.device("cuda:0")

@@ -12,7 +12,8 @@ the lowest prediction; `autotune(..., top_k)` times the k best predictions
 and keeps the fastest (k = 24 is exhaustive search, the fallback and the
 yardstick the regret is measured against).
 
-    python -m paper_1203_2946_amd.selector collect OUT.npz [--count N] [--max-seconds S]
+    python -m paper_1203_2946_amd.selector collect OUT.npz [--count N] [--start K] [--max-seconds S]
+    python -m paper_1203_2946_amd.selector merge OUT.npz PART1.npz PART2.npz ...
     python -m paper_1203_2946_amd.selector train DATA.npz WEIGHTS.npz
 """
 from __future__ import annotations
@@ -225,33 +226,45 @@ def sample_matrix(idx: int, seed: int, dev, max_nnz: int = 40_000_000):
     return fam, rp, ci, val, cols
 
 
-def collect(out_path: str, count: int = 2000, seed: int = 0, reps: int = 5, log=print, max_seconds: float = 1e9):
-    """Time all classes on matrices 0..count-1 of the data set; saves every
-    50 matrices and stops early (keeping what it has) after max_seconds."""
+def collect(out_path: str, count: int = 2000, seed: int = 0, reps: int = 5, log=print, max_seconds: float = 1e9,
+            start: int = 0):
+    """Time all classes on matrices start..count-1 of the data set; saves
+    every 50 matrices and stops early (keeping what it has) after
+    max_seconds.  Parts collected from different starts are joined with
+    `merge`."""
     dev = torch.device("cuda:0")
-    feats = np.zeros((count, N_FEATURES), np.float32)
-    times = np.zeros((count, N_CLASSES), np.float64)
-    meta_rows = np.zeros(count, np.int64)
-    meta_nnz = np.zeros(count, np.int64)
+    n = max(0, count - start)
+    feats = np.zeros((n, N_FEATURES), np.float32)
+    times = np.zeros((n, N_CLASSES), np.float64)
+    meta_rows = np.zeros(n, np.int64)
+    meta_nnz = np.zeros(n, np.int64)
     fams = []
     t0 = time.time()
     done = 0
-    for i in range(count):
+    for k in range(n):
         if time.time() - t0 > max_seconds:
             break
-        fam, rp, ci, val, cols = sample_matrix(i, seed, dev)
-        feats[i] = features(rp, ci, cols).cpu().numpy()
+        fam, rp, ci, val, cols = sample_matrix(start + k, seed, dev)
+        feats[k] = features(rp, ci, cols).cpu().numpy()
         runner = ClassRunner(rp, ci, val, cols)
-        times[i] = runner.time_classes(reps=reps)
-        meta_rows[i], meta_nnz[i] = rp.numel() - 1, ci.numel()
+        times[k] = runner.time_classes(reps=reps)
+        meta_rows[k], meta_nnz[k] = rp.numel() - 1, ci.numel()
         fams.append(fam)
-        done = i + 1
+        done = k + 1
         del runner, rp, ci, val
         if done % 50 == 0:
-            log(f"[collect] {done}/{count} matrices ({time.time() - t0:.0f}s)")
+            log(f"[collect] {start + done}/{count} matrices ({time.time() - t0:.0f}s)")
             _save(out_path, feats, times, meta_rows, meta_nnz, fams, done)
     _save(out_path, feats, times, meta_rows, meta_nnz, fams, done)
-    log(f"[collect] done: {done} matrices ({time.time() - t0:.0f}s)")
+    log(f"[collect] done: matrices {start}..{start + done - 1} ({time.time() - t0:.0f}s)")
+    return out_path
+
+
+def merge(out_path: str, parts) -> str:
+    """Join data files collected from consecutive starts, in the order given."""
+    ds = [np.load(p, allow_pickle=False) for p in parts]
+    keys = ("features", "times_ms", "rows", "nnz", "family")
+    np.savez(out_path, **{k: np.concatenate([d[k] for d in ds]) for k in keys}, classes=ds[0]["classes"])
     return out_path
 
 
@@ -291,7 +304,11 @@ def main(argv):
     if len(argv) >= 2 and argv[0] == "collect":
         count = int(argv[argv.index("--count") + 1]) if "--count" in argv else 2000
         secs = float(argv[argv.index("--max-seconds") + 1]) if "--max-seconds" in argv else 1e9
-        collect(argv[1], count=count, max_seconds=secs, log=lambda s: print(s, file=sys.stderr, flush=True))
+        start = int(argv[argv.index("--start") + 1]) if "--start" in argv else 0
+        collect(argv[1], count=count, max_seconds=secs, start=start,
+                log=lambda s: print(s, file=sys.stderr, flush=True))
+    elif len(argv) >= 3 and argv[0] == "merge":
+        merge(argv[1], argv[2:])
     elif len(argv) >= 3 and argv[0] == "train":
         model, rep = train_from_data(argv[1])
         np.savez(argv[2], params=model.params.cpu().numpy(), n_train=rep["n_train"])
