@@ -12,7 +12,9 @@
 // spreads the reads of one instruction over distinct banks too.  From 3
 // right-hand sides on (and for every bucket of the batched kernel) the steps
 // are software-pipelined: each step issues the next step's stream loads
-// before adding its own products (spmm_tile).
+// before adding its own products (spmm_tile).  Where a row piece spans two or
+// four 16-byte chunks, groups of adjacent lanes share their entries and each
+// lane gathers one chunk of every piece of its group (chunk lanes, below).
 //
 // The batched path runs that body from one persistent kernel: waves take
 // work tiles (a matrix and a range of its strips) from per-XCD queue counters
@@ -167,15 +169,123 @@ __device__ inline void spmm_accumulate(const SpmmMat& m, int base, int G, int hi
     }
 }
 
+// Chunk lanes.  From two 16-byte chunks per row piece on (4 or 8 fp64
+// right-hand-side slots, 8 fp32 ones), each group of C = 2^CL consecutive
+// lanes (a pair or a quad) shares the work of its C lanes' entries: lane c of
+// the group gathers chunk c of every one of those C row pieces and adds the
+// products for its own XV slots c * XV .. c * XV + XV - 1.  A gather
+// instruction then touches 64 / C row pieces, each read whole by C adjacent
+// lanes, instead of 64 pieces read a chunk at a time: with X in L2 such
+// gathers run ~1.45x faster for 64-byte pieces, since the vector-memory
+// address path handles each distinct line of an instruction separately.  The
+// stream loads stay one entry per lane; the C words and values of a group are
+// exchanged with DPP quad permutations (no LDS).  Lane c of a group owns
+// partial columns of the slots of chunk c only; the others stay +0.0.
+
+// The value of lane `src` of this lane's group of 2^CL lanes (CL = 1: pairs
+// (0, 1), (2, 3) of each quad; CL = 2: the quad).  src must fold to a
+// constant (the loops calling it are unrolled).
+template <int CL>
+__device__ inline int group_read(int v, int src) {
+    static_assert(CL == 1 || CL == 2, "pairs or quads");
+    // quad_perm selectors: [s, s, s, s] for a quad, [s, s, 2 + s, 2 + s] for pairs.
+    if constexpr (CL == 2) {
+        switch (src) {
+            case 0: return __builtin_amdgcn_mov_dpp(v, 0x00, 0xf, 0xf, false);
+            case 1: return __builtin_amdgcn_mov_dpp(v, 0x55, 0xf, 0xf, false);
+            case 2: return __builtin_amdgcn_mov_dpp(v, 0xaa, 0xf, 0xf, false);
+            default: return __builtin_amdgcn_mov_dpp(v, 0xff, 0xf, 0xf, false);
+        }
+    } else {
+        return src == 0 ? __builtin_amdgcn_mov_dpp(v, 0xa0, 0xf, 0xf, false)
+                        : __builtin_amdgcn_mov_dpp(v, 0xf5, 0xf, 0xf, false);
+    }
+}
+template <int CL>
+__device__ inline uint32_t group_read(uint32_t v, int src) {
+    return static_cast<uint32_t>(group_read<CL>(static_cast<int>(v), src));
+}
+template <int CL>
+__device__ inline float group_read(float v, int src) {
+    return __int_as_float(group_read<CL>(__float_as_int(v), src));
+}
+template <int CL>
+__device__ inline double group_read(double v, int src) {
+    const long long b = __double_as_longlong(v);
+    const uint32_t lo = group_read<CL>(static_cast<uint32_t>(b), src);
+    const uint32_t hi = group_read<CL>(static_cast<uint32_t>(static_cast<unsigned long long>(b) >> 32), src);
+    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
+// Chunk c of the row pieces of the group's U * C entries (entry u * C + j is
+// lane j's entry u): one 16-byte load each, elements st .. st + XV - 1 with
+// st = c * XV, moved back to st = nrhs - XV when the chunk would reach past
+// nrhs.  Clamped entries gather their clamped entry's piece, a valid address.
+template <int U, int CL, typename XT>
+__device__ inline void spmm_gather_chunk(const SpmmMat& m, const uint32_t (&w)[U], int st,
+                                         XT (&xc)[U << CL][16 / sizeof(XT)]) {
+    constexpr int C = 1 << CL;
+    constexpr int XV = static_cast<int>(16 / sizeof(XT));
+    typedef typename XLoose<XT>::type XL;
+    const XT* __restrict__ x = static_cast<const XT*>(m.x) + st;
+    const size_t ldx = static_cast<size_t>(m.ldx);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            const XL t = *reinterpret_cast<const XL*>(x + static_cast<size_t>(group_read<CL>(w[u], j) >> m.bits) * ldx);
+#pragma unroll
+            for (int q = 0; q < XV; ++q) xc[u * C + j][q] = t[q];
+        }
+    }
+}
+
+// The products of the group's U * C entries with this lane's chunk, added to
+// slots st .. st + XV - 1 of the lane's own partial column, with no branch
+// (clamped entries add +0.0, as in spmm_accumulate).  Entry u * C + j is lane
+// j's entry u of the step: index base - c + j + u * G.  A chunk moved back
+// (st < c * XV) also adds to slots below c * XV, which belong to chunk c - 1:
+// in this lane's column those are never read (the row sums of slot k read
+// the lanes of chunk k / XV only) and are cleared with the rest.
+template <int HB, int U, int RB, int CL, typename VT, typename XT, typename AT>
+__device__ inline void spmm_accumulate_chunk(const SpmmMat& m, int base, int G, int hi, int c, int st,
+                                             const uint32_t (&w)[U], const VT (&v)[U],
+                                             const XT (&xc)[U << CL][16 / sizeof(XT)], AT* __restrict__ buf,
+                                             int lane) {
+    constexpr int C = 1 << CL;
+    constexpr int XV = static_cast<int>(16 / sizeof(XT));
+    const uint32_t mask = (1u << m.bits) - 1u;
+    AT* mine = buf + st * kWave + lane;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const AT a = static_cast<AT>(ValTraits<VT>::widen(v[u]));
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            const bool ok = base - c + j + u * G < hi;
+            const uint32_t wj = group_read<CL>(w[u], j);
+            const AT aj = group_read<CL>(a, j);
+            AT* slot = mine + static_cast<int>(wj & mask & (HB - 1)) * RB * kWave;
+#pragma unroll
+            for (int q = 0; q < XV; ++q) {
+                const AT p = aj * static_cast<AT>(xc[u * C + j][q]);
+                lds_add(slot + q * kWave, ok ? p : AT(0));
+            }
+        }
+    }
+}
+
 // Row sums of the pass over strips [sb, sb + S) (those below s_end), written
 // to Y, and the partials cleared for the next pass.  Output o: strip slot
 // so = o mod S (fastest), partial i = o / S with i = row * RB + k; it sums
-// the G entry slots starting at slot i mod G.
-template <int HB, int RB, typename XT, typename AT>
+// the G entry slots starting at slot i mod G.  With chunk lanes (CL > 0)
+// only the G / C lanes of chunk k / XV hold partials of slot k: it sums
+// those, starting at the (i mod G/C)-th.
+template <int HB, int RB, typename XT, typename AT, int CL = 0>
 __device__ inline void spmm_finish(const SpmmMat& m, int sb, int s_end, AT* __restrict__ buf, int lane) {
     constexpr int SLOTS = HB * RB;
+    constexpr int XV = static_cast<int>(16 / sizeof(XT));
     const int g_log = m.g_log;
-    const int G = 1 << g_log;
+    const int G = 1 << (g_log - CL);
     const int s_log = 6 - g_log;
     const int nout = SLOTS << s_log;
     XT* __restrict__ y = static_cast<XT*>(m.y);
@@ -186,18 +296,18 @@ __device__ inline void spmm_finish(const SpmmMat& m, int sb, int s_end, AT* __re
         const int i = o >> s_log;
         const int k = i & (RB - 1);
         const int rr = i / RB;
-        const AT* p = buf + i * kWave + (so << g_log);
+        const AT* p = buf + i * kWave + (so << g_log) + (CL > 0 ? k / XV : 0);
         AT sum = AT(0);
         // Eight reads in flight at a time, added in the same order.
         int q = 0;
         for (; q + 8 <= G; q += 8) {
             AT t[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) t[j] = p[(q + j + i) & (G - 1)];
+            for (int j = 0; j < 8; ++j) t[j] = p[((q + j + i) & (G - 1)) << CL];
 #pragma unroll
             for (int j = 0; j < 8; ++j) sum += t[j];
         }
-        for (; q < G; ++q) sum += p[(q + i) & (G - 1)];
+        for (; q < G; ++q) sum += p[((q + i) & (G - 1)) << CL];
         const int strip = sb + so;
         const long long row = static_cast<long long>(strip) * m.height + rr;
         if (strip < s_end && rr < m.height && row < m.rows && k < m.nrhs)
@@ -219,10 +329,14 @@ __device__ inline void spmm_finish(const SpmmMat& m, int sb, int s_end, AT* __re
 // entries and strip indices), with no branch around it: at a branch the
 // compiler would have to assume the worst of the loads still in flight and
 // wait for the prefetch too.  The additions per lane and the reduction run in
-// the same order as without the pipelining.
-template <int HB, int RB, int NV, typename VT, typename XT, typename AT>
+// the same order as without the pipelining.  CL > 0: chunk lanes, groups of
+// 2^CL lanes sharing their entries (the group width G is at least 2^CL); the
+// stream loads are the same, a lane gathers and adds its chunk of the
+// group's entries instead of its own entries' whole pieces.
+template <int HB, int RB, int NV, typename VT, typename XT, typename AT, int CL = 0>
 __device__ inline void spmm_tile(const SpmmMat& m, int s0, int s1, AT* __restrict__ buf, int lane) {
     constexpr int U = SpmmUnroll<RB>::U;
+    constexpr int XV = static_cast<int>(16 / sizeof(XT));
     constexpr int SLOTS = HB * RB;
     const int g_log = m.g_log;
     const int G = 1 << g_log;
@@ -233,7 +347,7 @@ __device__ inline void spmm_tile(const SpmmMat& m, int s0, int s1, AT* __restric
     for (int i = 0; i < SLOTS; ++i) buf[i * kWave + lane] = AT(0);
     if (m.nnz == 0) {
         // No entries to load: every row sum is zero.
-        for (int sb = s0; sb < s1; sb += S) spmm_finish<HB, RB, XT, AT>(m, sb, s1, buf, lane);
+        for (int sb = s0; sb < s1; sb += S) spmm_finish<HB, RB, XT, AT, CL>(m, sb, s1, buf, lane);
         return;
     }
     // A lane whose strip is at or past s1 gets the empty range [sp[s1], sp[s1]).
@@ -244,19 +358,33 @@ __device__ inline void spmm_tile(const SpmmMat& m, int s0, int s1, AT* __restric
     uint32_t w[U];
     VT v[U];
     spmm_load_step<U, VT>(m, base, G, hi, w, v);
+    const int c = e & ((1 << CL) - 1);
+    const int st = min(c * XV, m.nrhs - XV);
     for (int sb = s0;;) {
-        XT xv[U][RB];
-        spmm_gather<U, RB, NV, XT>(m, w, xv);
+        // Chunk lanes: this lane's chunk of its group's row pieces; else the
+        // whole pieces of its own entries.
+        XT xv[CL > 0 ? (U << CL) : U][CL > 0 ? XV : RB];
+        if constexpr (CL > 0) {
+            spmm_gather_chunk<U, CL, XT>(m, w, st, xv);
+            // Every gather issued before anything that uses one (left alone,
+            // the scheduler interleaves each load with its multiplications
+            // and waits for it before issuing the next).
+            __builtin_amdgcn_sched_barrier(0);
+        } else
+            spmm_gather<U, RB, NV, XT>(m, w, xv);
         const int nb = base + U * G;
         const bool more = ballot(nb < hi) != 0ull;
         uint32_t w2[U];
         VT v2[U];
         spmm_load_step<U, VT>(m, more ? nb : lo_n + e, G, more ? hi : hi_n, w2, v2);
-        spmm_accumulate<HB, U, RB, VT, XT, AT>(m, base, G, hi, w, v, xv, buf, lane);
+        if constexpr (CL > 0)
+            spmm_accumulate_chunk<HB, U, RB, CL, VT, XT, AT>(m, base, G, hi, c, st, w, v, xv, buf, lane);
+        else
+            spmm_accumulate<HB, U, RB, VT, XT, AT>(m, base, G, hi, w, v, xv, buf, lane);
         if (more) {
             base = nb;
         } else {
-            spmm_finish<HB, RB, XT, AT>(m, sb, s1, buf, lane);
+            spmm_finish<HB, RB, XT, AT, CL>(m, sb, s1, buf, lane);
             sb += S;
             if (sb >= s1) break;
             s += S;
@@ -345,6 +473,17 @@ __device__ inline void spmm_tile_nv(const SpmmMat& m, int s0, int s1, AT* buf, i
         return;
     } else if constexpr (!VEC) {
         spmm_tile<HB, RB, 0, VT, XT, AT>(m, s0, s1, buf, lane);
+    } else if constexpr (RB / XV >= 2) {
+        // Chunk lanes when the group has room for them (nrhs > RB / 2 >= XV
+        // here, so every chunk is one 16-byte load).
+        constexpr int CL = RB / XV >= 4 ? 2 : 1;
+        if (m.g_log >= CL) {
+            spmm_tile<HB, RB, 0, VT, XT, AT, CL>(m, s0, s1, buf, lane);
+        } else if (m.nrhs == RB) {
+            spmm_tile<HB, RB, RB / XV, VT, XT, AT>(m, s0, s1, buf, lane);
+        } else {
+            spmm_tile<HB, RB, -1, VT, XT, AT>(m, s0, s1, buf, lane);
+        }
     } else {
         if (m.nrhs == RB)
             spmm_tile<HB, RB, RB / XV, VT, XT, AT>(m, s0, s1, buf, lane);

@@ -123,15 +123,20 @@ def test_spmm_groups_and_padded_blocks(C, group):
 
 
 @pytest.mark.parametrize("dtype,group,nrhs,ld", [("f64", 64, 8, 8), ("f64", 16, 5, 6), ("f64", 16, 4, 4),
-                                                  ("f64", 16, 7, 7), ("f32", 16, 7, 8), ("f32", 64, 3, 4)])
+                                                  ("f64", 16, 7, 7), ("f32", 16, 7, 8), ("f32", 64, 3, 4),
+                                                  ("f64", 4, 6, 6), ("f64", 2, 8, 9), ("f32", 2, 5, 5)])
 def test_spmm_several_passes_per_wave(C, dtype, group, nrhs, ld):
     """A single launch large enough that each wave takes 2-8 consecutive
     passes (the pipelined loop: the next step's loads are issued before this
     step's additions, clamped at strip and tile ends).  X rows 16-byte
     aligned with nrhs below the bucket (vector loads for the lower half of the
-    bucket, single loads above), and unaligned ones.  Columns within the
-    bounds; the persistent batched launch of the same matrix and group gives
-    the same bits."""
+    bucket, single loads above), and unaligned ones.  Chunk lanes (groups of 2
+    or 4 lanes sharing entries, each gathering one 16-byte chunk): with the
+    chunk moved back to end at nrhs (5-7 right-hand sides), with a group as
+    narrow as the chunk count (one entry slot per strip: fp64 group 4 with 4
+    chunks, fp32 group 2 with 2), and too narrow for them (fp64 group 2 with
+    4 chunks: one lane per entry).  Columns within the bounds; the persistent
+    batched launch of the same matrix and group gives the same bits."""
     A = synth.poisson_rows(400_000, 6.0, seed=nrhs + group)
     rp, ci, v, hv = G.upload(A, dtype)
     M = C.from_csr(rp, ci, v, A.cols, 2, sort=True)
