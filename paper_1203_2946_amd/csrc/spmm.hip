@@ -221,6 +221,8 @@ __device__ inline double group_read(double v, int src) {
 // lane j's entry u): one 16-byte load each, elements st .. st + XV - 1 with
 // st = c * XV, moved back to st = nrhs - XV when the chunk would reach past
 // nrhs.  Clamped entries gather their clamped entry's piece, a valid address.
+// Only the loads are issued here; the chunks are used after the next step's
+// stream loads are on their way.
 template <int U, int CL, typename XT>
 __device__ inline void spmm_gather_chunk(const SpmmMat& m, const uint32_t (&w)[U], int st,
                                          XT (&xc)[U << CL][16 / sizeof(XT)]) {
@@ -377,6 +379,10 @@ __device__ inline void spmm_tile(const SpmmMat& m, int s0, int s1, AT* __restric
         uint32_t w2[U];
         VT v2[U];
         spmm_load_step<U, VT>(m, more ? nb : lo_n + e, G, more ? hi : hi_n, w2, v2);
+        // The next step's stream loads issued before the first use of a gather
+        // (else the multiplications are hoisted above them and the prefetch
+        // waits for every gather).
+        if constexpr (CL > 0) __builtin_amdgcn_sched_barrier(0);
         if constexpr (CL > 0)
             spmm_accumulate_chunk<HB, U, RB, CL, VT, XT, AT>(m, base, G, hi, c, st, w, v, xv, buf, lane);
         else
