@@ -949,25 +949,6 @@ __global__ __launch_bounds__(kConvThreads) void from_csr_rows_kernel(
 
 // ------------------------------------------------------------------ list kernels
 
-// Sorted conversion of the listed strips of at most kWaveSortCap entries: one
-// wave per strip, strips taken in a grid-stride loop.
-template <int HB, typename ET>
-__global__ __launch_bounds__(kConvThreads) void sort_list_wave_kernel(
-    int rows, int height, int bits, const int* __restrict__ row_ptr, const int* __restrict__ col_ind,
-    const ET* __restrict__ val_in, uint32_t* __restrict__ col_word, ET* __restrict__ val_out,
-    const int* __restrict__ ws_count, const int* __restrict__ ws_small) {
-    __shared__ uint64_t keys[kConvWaves][kWaveSortCap];
-    __shared__ int rtab[kConvWaves][HB + 1];
-    const int lane = lane_id();
-    const int wave = uniform(static_cast<int>(threadIdx.x) / kWave);
-    const int count = ws_count[0];
-    const int nwaves = static_cast<int>(gridDim.x) * kConvWaves;
-    for (int item = static_cast<int>(blockIdx.x) * kConvWaves + wave; item < count; item += nwaves)
-        sort_strip_mid<HB, kWaveSortCap / kWave, ET>(ws_small[item], rows, height, bits, row_ptr, col_ind, val_in,
-                                                     col_word, val_out, keys[wave], rtab[wave], lane);
-}
-
-
 // One listed long strip of n entries by the whole 1024-thread workgroup, in K
 // (LDS, or the strip's workspace slice of 2n 64-bit words when keys_global;
 // passes over global memory then need an agent-scope fence before the
@@ -1299,64 +1280,81 @@ __device__ inline int strip_row_ptr(int strip, int rows, int height, const int* 
     return lane <= min(height, rows - r0) ? row_ptr[r0 + lane] : INT_MAX;
 }
 
-// Sorted conversion of the listed long strips (more than kWaveSortCap
-// entries): one 1024-thread workgroup per CU; workgroup b takes list entry b
-// first, then the next untaken entry of a shared counter (ws_count[2], zero at
-// launch), so strips of very different lengths still spread evenly.  In LDS
-// when the strip fits (n <= kBlockSortCap, rank_strip_block), else in the
-// strip's own slice of the workspace [2*s0, 2*s1) (sort_strip_block).  A
-// strip costs a chain of dependent global loads (list entry, row pointers,
-// then entries); the next strip's list entry and row pointers are loaded
-// while the current one is sorted.
+// Sorted conversion of the listed strips, both lists in one launch of one
+// 1024-thread workgroup per CU.  First the long strips (more than
+// kWaveSortCap entries): workgroup b takes list entry b first, then the next
+// untaken entry of a shared counter (ws_count[2], zero at launch), so strips
+// of very different lengths still spread evenly.  In LDS when the strip fits
+// (n <= kBlockSortCap, rank_strip_block), else in the strip's own slice of
+// the workspace [2*s0, 2*s1) (sort_strip_block).  A strip costs a chain of
+// dependent global loads (list entry, row pointers, then entries); the next
+// strip's list entry and row pointers are loaded while the current one is
+// sorted.  Then the short listed strips (at most kWaveSortCap entries): each
+// of the workgroup's 16 waves takes the next one from a second counter
+// (ws_count[3], zero at launch) and sorts it alone in its sixteenth of the
+// key buffer.  A workgroup whose long strips are done (or that drew none)
+// goes on to the short ones while others still sort long strips: run as two
+// launches, the CUs left idle by the last long strips waited for them.
 template <int HB, typename ET>
-__global__ __launch_bounds__(kBlockSortThreads) void sort_list_block_kernel(
+__global__ __launch_bounds__(kBlockSortThreads) void sort_lists_kernel(
     int rows, int height, int bits, const int* __restrict__ row_ptr, const int* __restrict__ col_ind,
     const ET* __restrict__ val_in, uint32_t* __restrict__ col_word, ET* __restrict__ val_out,
-    int* __restrict__ ws_count, const int* __restrict__ ws_big, uint64_t* __restrict__ gkeys) {
+    int* __restrict__ ws_count, const int* __restrict__ ws_small, const int* __restrict__ ws_big,
+    uint64_t* __restrict__ gkeys) {
+    constexpr int NW = kBlockSortThreads / kWave;
+    static_assert(kBlockSortCap >= NW * kWaveSortCap, "a short strip's keys per wave");
     __shared__ uint64_t skeys[kBlockSortCap];
     __shared__ int rt[HB + 1];
     __shared__ int taken[2];
+    __shared__ int wrt[NW][HB + 1];
     const int tid = static_cast<int>(threadIdx.x);
     const int lane = lane_id();
-    const int wave = tid / kWave;
+    const int wave = uniform(tid / kWave);
     const int count = ws_count[1];
     int item = static_cast<int>(blockIdx.x);
-    if (item >= count) return;
-    if (tid == 0) taken[0] = static_cast<int>(gridDim.x) + atomicAdd(&ws_count[2], 1);
-    int strip = ws_big[item];
-    int myrp = strip_row_ptr(strip, rows, height, row_ptr, lane);
-    __syncthreads();
-    int next = taken[0];
-    for (int k = 1; item < count; ++k) {
-        // The entry after `next` is taken now and read after this strip's
-        // last barrier (taken[] alternates, so it is not overwritten early).
-        if (tid == 0 && next < count) taken[k & 1] = static_cast<int>(gridDim.x) + atomicAdd(&ws_count[2], 1);
-        StripRows sr;
-        sr.r0 = strip * height;
-        sr.nr = min(height, rows - sr.r0);
-        sr.myrp = myrp;
-        sr.s0 = __shfl(myrp, 0);
-        sr.s1 = __shfl(myrp, sr.nr);
-        const int n = sr.s1 - sr.s0;
-        const int nstrip = next < count ? ws_big[next] : 0;
-        int nmyrp = INT_MAX;
-        const auto prefetch = [&] {
-            if (next < count) nmyrp = strip_row_ptr(nstrip, rows, height, row_ptr, lane);
-        };
-        if (n <= kBlockSortCap) {
-            rank_strip_block<HB, kBlockSortThreads, ET>(sr, n, bits, col_ind, val_in, col_word, val_out, skeys,
-                                                        tid, prefetch);
-        } else {
-            prefetch();
-            sort_strip_block<HB, ET>(sr, n, bits, col_ind, val_in, col_word, val_out,
-                                     gkeys + 2 * static_cast<size_t>(sr.s0), true, rt, tid, wave, lane);
+    if (item < count) {
+        if (tid == 0) taken[0] = static_cast<int>(gridDim.x) + atomicAdd(&ws_count[2], 1);
+        int strip = ws_big[item];
+        int myrp = strip_row_ptr(strip, rows, height, row_ptr, lane);
+        __syncthreads();
+        int next = taken[0];
+        for (int k = 1; item < count; ++k) {
+            // The entry after `next` is taken now and read after this strip's
+            // last barrier (taken[] alternates, so it is not overwritten early).
+            if (tid == 0 && next < count) taken[k & 1] = static_cast<int>(gridDim.x) + atomicAdd(&ws_count[2], 1);
+            StripRows sr;
+            sr.r0 = strip * height;
+            sr.nr = min(height, rows - sr.r0);
+            sr.myrp = myrp;
+            sr.s0 = __shfl(myrp, 0);
+            sr.s1 = __shfl(myrp, sr.nr);
+            const int n = sr.s1 - sr.s0;
+            const int nstrip = next < count ? ws_big[next] : 0;
+            int nmyrp = INT_MAX;
+            const auto prefetch = [&] {
+                if (next < count) nmyrp = strip_row_ptr(nstrip, rows, height, row_ptr, lane);
+            };
+            if (n <= kBlockSortCap) {
+                rank_strip_block<HB, kBlockSortThreads, ET>(sr, n, bits, col_ind, val_in, col_word, val_out, skeys,
+                                                            tid, prefetch);
+            } else {
+                prefetch();
+                sort_strip_block<HB, ET>(sr, n, bits, col_ind, val_in, col_word, val_out,
+                                         gkeys + 2 * static_cast<size_t>(sr.s0), true, rt, tid, wave, lane);
+            }
+            __syncthreads();  // the next item reuses skeys and rt
+            item = next;
+            next = next < count ? taken[k & 1] : count;
+            strip = nstrip;
+            myrp = nmyrp;
         }
-        __syncthreads();  // the next item reuses skeys and rt
-        item = next;
-        next = next < count ? taken[k & 1] : count;
-        strip = nstrip;
-        myrp = nmyrp;
     }
+    const int scount = ws_count[0];
+    uint64_t* slice = skeys + wave * kWaveSortCap;
+    const int nwaves = static_cast<int>(gridDim.x) * NW;
+    for (int it = static_cast<int>(blockIdx.x) * NW + wave; it < scount; it += nwaves)
+        sort_strip_mid<HB, kWaveSortCap / kWave, ET>(ws_small[it], rows, height, bits, row_ptr, col_ind, val_in,
+                                                     col_word, val_out, slice, wrt[wave], lane);
 }
 
 __global__ void validate_csr_kernel(int rows, int cols, int nnz, const int* __restrict__ row_ptr,
@@ -1382,14 +1380,17 @@ struct Conv {
     int rows, strips, height, bits, nnz;
 };
 
-// The listed strips of more than kWaveSortCap entries: one workgroup per CU.
+// Both lists of strips the first kernel could not sort (sort_lists_kernel):
+// one workgroup per CU, or fewer when the lists cannot be that long.
 template <int HB, typename ET>
-void launch_sort_lists_big(const Conv& cv, const FromCsrWorkspaceLayout& L, const int* row_ptr, const int* col_ind,
-                           const ET* vin, uint32_t* col_word, ET* vout, int* ws_count, const int* ws_big,
-                           uint64_t* gkeys, hipStream_t stream) {
-    const int g = static_cast<int>(L.big_cap < kBlockSortGrid ? L.big_cap : kBlockSortGrid);
-    hipLaunchKernelGGL((sort_list_block_kernel<HB, ET>), dim3(g), dim3(kBlockSortThreads), 0, stream, cv.rows,
-                       cv.height, cv.bits, row_ptr, col_ind, vin, col_word, vout, ws_count, ws_big, gkeys);
+void launch_sort_lists(const Conv& cv, const FromCsrWorkspaceLayout& L, const int* row_ptr, const int* col_ind,
+                       const ET* vin, uint32_t* col_word, ET* vout, int* ws_count, const int* ws_small,
+                       const int* ws_big, uint64_t* gkeys, hipStream_t stream) {
+    constexpr size_t NW = kBlockSortThreads / kWave;
+    const size_t want = std::max<size_t>(L.big_cap, (L.small_cap + NW - 1) / NW);
+    const int g = static_cast<int>(std::max<size_t>(1, std::min<size_t>(want, kBlockSortGrid)));
+    hipLaunchKernelGGL((sort_lists_kernel<HB, ET>), dim3(g), dim3(kBlockSortThreads), 0, stream, cv.rows,
+                       cv.height, cv.bits, row_ptr, col_ind, vin, col_word, vout, ws_count, ws_small, ws_big, gkeys);
 }
 
 template <int G, int E, int HB, typename ET>
@@ -1406,20 +1407,17 @@ hipError_t from_csr_g(const Conv& cv, const int* row_ptr, const int* col_ind, co
     int* ws_small = reinterpret_cast<int*>(ws + L.small_off);
     int* ws_big = reinterpret_cast<int*>(ws + L.big_off);
     auto* gkeys = reinterpret_cast<uint64_t*>(ws + L.global_off);
-    hipLaunchKernelGGL(set_ints_kernel, dim3(1), dim3(64), 0, stream, ws_count, 3, 0);
+    hipLaunchKernelGGL(set_ints_kernel, dim3(1), dim3(64), 0, stream, ws_count, 4, 0);
     hipLaunchKernelGGL((from_csr_group_kernel<HB, G, E, ET>), dim3(blocks), dim3(kConvThreads), 0, stream,
                        cv.rows, cv.strips, cv.height, cv.bits, cv.nnz, row_ptr, col_ind, vin, strip_ptr, col_word,
                        vout, ws_count, ws_small, ws_big);
-    const size_t small_blocks = (L.small_cap + kConvWaves - 1) / kConvWaves;
-    const int g1 = static_cast<int>(small_blocks < 1024 ? small_blocks : 1024);
-    hipLaunchKernelGGL((sort_list_wave_kernel<HB, ET>), dim3(g1), dim3(kConvThreads), 0, stream, cv.rows, cv.height,
-                       cv.bits, row_ptr, col_ind, vin, col_word, vout, ws_count, ws_small);
-    launch_sort_lists_big<HB, ET>(cv, L, row_ptr, col_ind, vin, col_word, vout, ws_count, ws_big, gkeys, stream);
+    launch_sort_lists<HB, ET>(cv, L, row_ptr, col_ind, vin, col_word, vout, ws_count, ws_small, ws_big, gkeys,
+                              stream);
     return hipGetLastError();
 }
 
 // Tall strips: the bucket kernel (one wave per strip of up to kWaveSortCap
-// entries), then the same list kernels for longer strips.
+// entries), then the same list kernel for longer strips.
 template <int HB, typename ET>
 hipError_t from_csr_bucket(const Conv& cv, const int* row_ptr, const int* col_ind, const void* val_in,
                            int* strip_ptr, uint32_t* col_word, void* val_out, void* workspace, hipStream_t stream) {
@@ -1433,11 +1431,12 @@ hipError_t from_csr_bucket(const Conv& cv, const int* row_ptr, const int* col_in
     int* ws_small = reinterpret_cast<int*>(ws + L.small_off);
     int* ws_big = reinterpret_cast<int*>(ws + L.big_off);
     auto* gkeys = reinterpret_cast<uint64_t*>(ws + L.global_off);
-    hipLaunchKernelGGL(set_ints_kernel, dim3(1), dim3(64), 0, stream, ws_count, 3, 0);
+    hipLaunchKernelGGL(set_ints_kernel, dim3(1), dim3(64), 0, stream, ws_count, 4, 0);
     hipLaunchKernelGGL((from_csr_bucket_kernel<HB, E, ET>), dim3(blocks), dim3(kConvThreads), 0, stream, cv.rows,
                        cv.strips, cv.height, cv.bits, cv.nnz, row_ptr, col_ind, vin, strip_ptr, col_word, vout,
                        ws_count, ws_small, ws_big);
-    launch_sort_lists_big<HB, ET>(cv, L, row_ptr, col_ind, vin, col_word, vout, ws_count, ws_big, gkeys, stream);
+    launch_sort_lists<HB, ET>(cv, L, row_ptr, col_ind, vin, col_word, vout, ws_count, ws_small, ws_big, gkeys,
+                              stream);
     return hipGetLastError();
 }
 
