@@ -280,6 +280,26 @@ def _rows_matrix(rng, rows, cols, lengths, col_fn, canonical=True):
     return synth.Csr(rows, cols, rp.astype(np.int32), col, rng.standard_normal(col.size))
 
 
+@pytest.mark.parametrize("height", [4, 8])
+def test_both_lists_many_mid_strips(C, height):
+    """One launch sorts both lists of strips the group kernel leaves: more
+    mid-size strips (257..1024 entries, one wave each) than the launch has
+    waves (256 workgroups x 16), so waves take several in turn, together with
+    long strips (one workgroup each) that hold a few workgroups back while
+    the others start on the mid-size ones."""
+    rng = np.random.default_rng(77 + height)
+    strips = 5000
+    rows, cols = strips * height, 1 << 20
+    k = rng.integers(300 // height, 1000 // height, rows)
+    k[[3, 4000, rows - 1]] = 3000                                         # three long strips
+    A = _rows_matrix(rng, rows, cols, k, lambda i, n: rng.choice(cols, n, replace=False))
+    per_strip = np.add.reduceat(np.diff(A.row_ptr), np.arange(0, rows, height))
+    assert int(np.sum((per_strip > 256) & (per_strip <= 1024))) > 256 * 16
+    assert int(np.sum(per_strip > 1024)) == 3
+    M, hv = check_from_csr(C, A, height, True)
+    check_round_trip(C, A, M, hv)
+
+
 @pytest.mark.parametrize("height", [16, 32])
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 def test_tall_strips_bucket_sort(C, height, dtype):
