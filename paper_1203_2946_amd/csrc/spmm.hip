@@ -25,6 +25,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "cmrs_device.hpp"
@@ -50,6 +51,26 @@ template <int RB>
 struct SpmmUnroll {
     static constexpr int U = RB >= 4 ? 4 : 8;  // entries per lane in one step
 };
+
+// Chunk lanes (below) for a matrix: log2 of the lanes per group, or 0.  Used
+// alike on the host (LDS sizes) and in the kernels (which path runs).  xv:
+// X values per 16 bytes; a group needs at least two chunks per row piece, a
+// group width of at least C lanes and a whole vector of entries in the
+// matrix; bf16 values (2-byte aligned) stay on single loads.
+__host__ __device__ inline int spmm_chunk_log(const SpmmMat& m, int xv, bool bf16) {
+    const int rb = 1 << m.rb_log;
+    if (bf16 || rb < 2 * xv) return 0;
+    const int cl = rb >= 4 * xv ? 2 : 1;
+    return m.g_log >= cl && m.nnz >= (1 << cl) ? cl : 0;
+}
+
+// Partial slots per lane: HB * RB, or HB * XV with chunk lanes in fp64 (a
+// lane keeps the slots of its own chunk only: a quarter or half of the LDS,
+// so more waves fit; fp32 chunk lanes keep the full layout, measured faster
+// there).
+__host__ __device__ inline int spmm_lane_slots(const SpmmMat& m, int xv, bool bf16) {
+    return m.hb * (xv == 2 && spmm_chunk_log(m, xv, bf16) > 0 ? xv : (1 << m.rb_log));
+}
 
 // The stream loads of one step of a lane: the packed words and values of
 // entries base, base + G, ..., base + (U - 1) G of its strip.  Entries past
@@ -217,14 +238,82 @@ __device__ inline double group_read(double v, int src) {
     return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
 }
 
-// Chunk c of the row pieces of the group's U * C entries (entry u * C + j is
-// lane j's entry u): one 16-byte load each, elements st .. st + XV - 1 with
-// st = c * XV, moved back to st = nrhs - XV when the chunk would reach past
-// nrhs.  Clamped entries gather their clamped entry's piece, a valid address.
-// Only the loads are issued here; the chunks are used after the next step's
-// stream loads are on their way.
-template <int U, int CL, typename XT>
-__device__ inline void spmm_gather_chunk(const SpmmMat& m, const uint32_t (&w)[U], int st,
+// C consecutive stream elements at their own alignment (a multi-dword load
+// needs dword alignment only).
+template <typename T, int C>
+struct SVec;
+template <int C>
+struct SVec<uint32_t, C> {
+    typedef uint32_t type __attribute__((ext_vector_type(C), aligned(4)));
+};
+template <int C>
+struct SVec<double, C> {
+    typedef double type __attribute__((ext_vector_type(C), aligned(8)));
+};
+template <int C>
+struct SVec<float, C> {
+    typedef float type __attribute__((ext_vector_type(C), aligned(4)));
+};
+
+// The stream data of one step of a chunk-lane group.  The group's entries at
+// step offset u are the C consecutive entries g + u * G + j, j < C (g: the
+// group's first entry slot); lane c loads those of the offsets u = k * C + c
+// as one vector of words and one of values (the vector-memory address path
+// costs about the same per lane whatever the width, so this is C times fewer
+// addresses than a word and a value per lane and entry).  A vector that
+// would reach past the last entry of the matrix is moved back to end there,
+// d[k] places later than wanted; one wholly past its strip is moved to the
+// strip's last entry.  Elements are then picked at min(j + d, C - 1): the
+// wanted one for every entry inside the strip, a valid one otherwise.
+template <int U, int CL, typename VT>
+struct ChunkStream {
+    static constexpr int C = 1 << CL;
+    static constexpr int NV = U >> CL;
+    typename SVec<uint32_t, C>::type w[NV];
+    typename SVec<VT, C>::type v[NV];
+    int d[NV];
+};
+
+template <int U, int CL, typename VT>
+__device__ inline void spmm_load_chunk(const SpmmMat& m, int g, int G, int hi, int c, ChunkStream<U, CL, VT>& t) {
+    typedef ChunkStream<U, CL, VT> CS;
+    typedef typename SVec<uint32_t, CS::C>::type WV;
+    typedef typename SVec<VT, CS::C>::type VV;
+    const VT* __restrict__ val = static_cast<const VT*>(m.val);
+#pragma unroll
+    for (int k = 0; k < CS::NV; ++k) {
+        const int j = g + (k * CS::C + c) * G;
+        const int jv = max(min(min(j, hi - 1), m.nnz - CS::C), 0);
+        t.d[k] = j - jv;
+        t.w[k] = __builtin_nontemporal_load(reinterpret_cast<const WV*>(m.word + jv));
+        t.v[k] = __builtin_nontemporal_load(reinterpret_cast<const VV*>(val + jv));
+    }
+}
+
+// Element j of this lane's vector k, placed as described above.
+template <int C, typename V>
+__device__ inline auto chunk_pick(const V& vec, int d, int j) -> decltype(vec[0] + vec[0]) {
+    const int p = min(j + d, C - 1);
+    auto r = vec[C - 1];
+#pragma unroll
+    for (int q = C - 2; q >= 0; --q) r = p == q ? vec[q] : r;
+    return r;
+}
+
+// The word of the group's entry (u, j), read from the lane that loaded it.
+template <int U, int CL, typename VT>
+__device__ inline uint32_t chunk_word(const ChunkStream<U, CL, VT>& t, int u, int j) {
+    constexpr int C = 1 << CL;
+    return group_read<CL>(chunk_pick<C>(t.w[u >> CL], t.d[u >> CL], j), u & (C - 1));
+}
+
+// Chunk c of the row pieces of the group's U * C entries: one 16-byte load
+// each, elements st .. st + XV - 1 with st = c * XV, moved back to st = nrhs
+// - XV when the chunk would reach past nrhs.  Entries past their strip's end
+// gather the piece of a valid word.  Only the loads are issued here; the
+// chunks are used after the next step's stream loads are on their way.
+template <int U, int CL, typename VT, typename XT>
+__device__ inline void spmm_gather_chunk(const SpmmMat& m, const ChunkStream<U, CL, VT>& t, int st,
                                          XT (&xc)[U << CL][16 / sizeof(XT)]) {
     constexpr int C = 1 << CL;
     constexpr int XV = static_cast<int>(16 / sizeof(XT));
@@ -235,42 +324,51 @@ __device__ inline void spmm_gather_chunk(const SpmmMat& m, const uint32_t (&w)[U
     for (int u = 0; u < U; ++u) {
 #pragma unroll
         for (int j = 0; j < C; ++j) {
-            const XL t = *reinterpret_cast<const XL*>(x + static_cast<size_t>(group_read<CL>(w[u], j) >> m.bits) * ldx);
+            const uint32_t wj = chunk_word<U, CL, VT>(t, u, j);
+            const XL v = *reinterpret_cast<const XL*>(x + static_cast<size_t>(wj >> m.bits) * ldx);
 #pragma unroll
-            for (int q = 0; q < XV; ++q) xc[u * C + j][q] = t[q];
+            for (int q = 0; q < XV; ++q) xc[u * C + j][q] = v[q];
         }
     }
 }
 
 // The products of the group's U * C entries with this lane's chunk, added to
-// slots st .. st + XV - 1 of the lane's own partial column, with no branch
-// (clamped entries add +0.0, as in spmm_accumulate).  Entry u * C + j is lane
-// j's entry u of the step: index base - c + j + u * G.  A chunk moved back
-// (st < c * XV) also adds to slots below c * XV, which belong to chunk c - 1:
-// in this lane's column those are never read (the row sums of slot k read
-// the lanes of chunk k / XV only) and are cleared with the rest.
+// the lane's own partials, with no branch (entries past their strip's end add
+// +0.0, as in spmm_accumulate).  Entry (u, j) is entry g + u * G + j of the
+// strip.  fp64: a lane keeps the XV slots of its chunk only, partial (row, q)
+// at [row * XV + q][lane] for right-hand side c * XV + q; a chunk moved back
+// by sh = c * XV - st elements holds right-hand side c * XV + q in element q
+// + sh, and its first sh elements (chunk c - 1's) add +0.0 to slot 0.  fp32:
+// the full layout [row * RB + k][lane], element q going to k = st + q; the
+// slots below c * XV that a moved-back chunk adds to are chunk c - 1's, never
+// read from this lane's column (the row sums of slot k read the lanes of
+// chunk k / XV only) and cleared with the rest.
 template <int HB, int U, int RB, int CL, typename VT, typename XT, typename AT>
-__device__ inline void spmm_accumulate_chunk(const SpmmMat& m, int base, int G, int hi, int c, int st,
-                                             const uint32_t (&w)[U], const VT (&v)[U],
+__device__ inline void spmm_accumulate_chunk(const SpmmMat& m, int g, int G, int hi, int c, int st,
+                                             const ChunkStream<U, CL, VT>& t,
                                              const XT (&xc)[U << CL][16 / sizeof(XT)], AT* __restrict__ buf,
                                              int lane) {
     constexpr int C = 1 << CL;
     constexpr int XV = static_cast<int>(16 / sizeof(XT));
+    constexpr bool COMPACT = sizeof(AT) == 8;
     const uint32_t mask = (1u << m.bits) - 1u;
-    AT* mine = buf + st * kWave + lane;
+    const int sh = c * XV - st;
+    AT* mine = COMPACT ? buf + lane : buf + st * kWave + lane;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const AT a = static_cast<AT>(ValTraits<VT>::widen(v[u]));
 #pragma unroll
         for (int j = 0; j < C; ++j) {
-            const bool ok = base - c + j + u * G < hi;
-            const uint32_t wj = group_read<CL>(w[u], j);
-            const AT aj = group_read<CL>(a, j);
-            AT* slot = mine + static_cast<int>(wj & mask & (HB - 1)) * RB * kWave;
+            const bool ok = g + u * G + j < hi;
+            const uint32_t wj = chunk_word<U, CL, VT>(t, u, j);
+            const AT aj = group_read<CL>(static_cast<AT>(chunk_pick<C>(t.v[u >> CL], t.d[u >> CL], j)), u & (C - 1));
+            AT* slot = mine + static_cast<int>(wj & mask & (HB - 1)) * (COMPACT ? XV : RB) * kWave;
 #pragma unroll
             for (int q = 0; q < XV; ++q) {
                 const AT p = aj * static_cast<AT>(xc[u * C + j][q]);
-                lds_add(slot + q * kWave, ok ? p : AT(0));
+                if constexpr (COMPACT)
+                    lds_add(slot + max(q - sh, 0) * kWave, ok && q >= sh ? p : AT(0));
+                else
+                    lds_add(slot + q * kWave, ok ? p : AT(0));
             }
         }
     }
@@ -279,13 +377,53 @@ __device__ inline void spmm_accumulate_chunk(const SpmmMat& m, int base, int G, 
 // Row sums of the pass over strips [sb, sb + S) (those below s_end), written
 // to Y, and the partials cleared for the next pass.  Output o: strip slot
 // so = o mod S (fastest), partial i = o / S with i = row * RB + k; it sums
-// the G entry slots starting at slot i mod G.  With chunk lanes (CL > 0)
-// only the G / C lanes of chunk k / XV hold partials of slot k: it sums
-// those, starting at the (i mod G/C)-th.
-template <int HB, int RB, typename XT, typename AT, int CL = 0>
+// the G entry slots starting at slot i mod G.
+template <int HB, int RB, typename XT, typename AT>
 __device__ inline void spmm_finish(const SpmmMat& m, int sb, int s_end, AT* __restrict__ buf, int lane) {
     constexpr int SLOTS = HB * RB;
+    const int g_log = m.g_log;
+    const int G = 1 << g_log;
+    const int s_log = 6 - g_log;
+    const int nout = SLOTS << s_log;
+    XT* __restrict__ y = static_cast<XT*>(m.y);
+    const size_t ldy = static_cast<size_t>(m.ldy);
+    wave_lds_sync();
+    for (int o = lane; o < nout; o += kWave) {
+        const int so = o & ((1 << s_log) - 1);
+        const int i = o >> s_log;
+        const int k = i & (RB - 1);
+        const int rr = i / RB;
+        const AT* p = buf + i * kWave + (so << g_log);
+        AT sum = AT(0);
+        // Eight reads in flight at a time, added in the same order.
+        int q = 0;
+        for (; q + 8 <= G; q += 8) {
+            AT t[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) t[j] = p[(q + j + i) & (G - 1)];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) sum += t[j];
+        }
+        for (; q < G; ++q) sum += p[(q + i) & (G - 1)];
+        const int strip = sb + so;
+        const long long row = static_cast<long long>(strip) * m.height + rr;
+        if (strip < s_end && rr < m.height && row < m.rows && k < m.nrhs)
+            y[static_cast<size_t>(row) * ldy + k] = static_cast<XT>(sum);
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int i = 0; i < SLOTS; ++i) buf[i * kWave + lane] = AT(0);
+}
+
+// spmm_finish for chunk lanes: output (row, k) sums the G / C lanes of chunk
+// k / XV (entry slot e = e' * C + k / XV), partial [row * XV + k mod XV] in
+// fp64 ([row * RB + k] in fp32), starting at the (i mod G/C)-th; the
+// partials are cleared.
+template <int HB, int RB, typename XT, typename AT, int CL>
+__device__ inline void spmm_finish_chunk(const SpmmMat& m, int sb, int s_end, AT* __restrict__ buf, int lane) {
     constexpr int XV = static_cast<int>(16 / sizeof(XT));
+    constexpr bool COMPACT = sizeof(AT) == 8;
+    constexpr int SLOTS = HB * RB;
     const int g_log = m.g_log;
     const int G = 1 << (g_log - CL);
     const int s_log = 6 - g_log;
@@ -298,9 +436,8 @@ __device__ inline void spmm_finish(const SpmmMat& m, int sb, int s_end, AT* __re
         const int i = o >> s_log;
         const int k = i & (RB - 1);
         const int rr = i / RB;
-        const AT* p = buf + i * kWave + (so << g_log) + (CL > 0 ? k / XV : 0);
+        const AT* p = buf + (COMPACT ? rr * XV + k % XV : i) * kWave + (so << g_log) + k / XV;
         AT sum = AT(0);
-        // Eight reads in flight at a time, added in the same order.
         int q = 0;
         for (; q + 8 <= G; q += 8) {
             AT t[8];
@@ -317,7 +454,7 @@ __device__ inline void spmm_finish(const SpmmMat& m, int sb, int s_end, AT* __re
     }
     wave_lds_sync();
 #pragma unroll
-    for (int i = 0; i < SLOTS; ++i) buf[i * kWave + lane] = AT(0);
+    for (int i = 0; i < HB * (COMPACT ? XV : RB); ++i) buf[i * kWave + lane] = AT(0);
 }
 
 // Strips [s0, s1) of matrix m in passes of S = 64 / G strips; buf holds the
@@ -335,10 +472,9 @@ __device__ inline void spmm_finish(const SpmmMat& m, int sb, int s_end, AT* __re
 // 2^CL lanes sharing their entries (the group width G is at least 2^CL); the
 // stream loads are the same, a lane gathers and adds its chunk of the
 // group's entries instead of its own entries' whole pieces.
-template <int HB, int RB, int NV, typename VT, typename XT, typename AT, int CL = 0>
+template <int HB, int RB, int NV, typename VT, typename XT, typename AT>
 __device__ inline void spmm_tile(const SpmmMat& m, int s0, int s1, AT* __restrict__ buf, int lane) {
     constexpr int U = SpmmUnroll<RB>::U;
-    constexpr int XV = static_cast<int>(16 / sizeof(XT));
     constexpr int SLOTS = HB * RB;
     const int g_log = m.g_log;
     const int G = 1 << g_log;
@@ -349,7 +485,7 @@ __device__ inline void spmm_tile(const SpmmMat& m, int s0, int s1, AT* __restric
     for (int i = 0; i < SLOTS; ++i) buf[i * kWave + lane] = AT(0);
     if (m.nnz == 0) {
         // No entries to load: every row sum is zero.
-        for (int sb = s0; sb < s1; sb += S) spmm_finish<HB, RB, XT, AT, CL>(m, sb, s1, buf, lane);
+        for (int sb = s0; sb < s1; sb += S) spmm_finish<HB, RB, XT, AT>(m, sb, s1, buf, lane);
         return;
     }
     // A lane whose strip is at or past s1 gets the empty range [sp[s1], sp[s1]).
@@ -360,37 +496,19 @@ __device__ inline void spmm_tile(const SpmmMat& m, int s0, int s1, AT* __restric
     uint32_t w[U];
     VT v[U];
     spmm_load_step<U, VT>(m, base, G, hi, w, v);
-    const int c = e & ((1 << CL) - 1);
-    const int st = min(c * XV, m.nrhs - XV);
     for (int sb = s0;;) {
-        // Chunk lanes: this lane's chunk of its group's row pieces; else the
-        // whole pieces of its own entries.
-        XT xv[CL > 0 ? (U << CL) : U][CL > 0 ? XV : RB];
-        if constexpr (CL > 0) {
-            spmm_gather_chunk<U, CL, XT>(m, w, st, xv);
-            // Every gather issued before anything that uses one (left alone,
-            // the scheduler interleaves each load with its multiplications
-            // and waits for it before issuing the next).
-            __builtin_amdgcn_sched_barrier(0);
-        } else
-            spmm_gather<U, RB, NV, XT>(m, w, xv);
+        XT xv[U][RB];
+        spmm_gather<U, RB, NV, XT>(m, w, xv);
         const int nb = base + U * G;
         const bool more = ballot(nb < hi) != 0ull;
         uint32_t w2[U];
         VT v2[U];
         spmm_load_step<U, VT>(m, more ? nb : lo_n + e, G, more ? hi : hi_n, w2, v2);
-        // The next step's stream loads issued before the first use of a gather
-        // (else the multiplications are hoisted above them and the prefetch
-        // waits for every gather).
-        if constexpr (CL > 0) __builtin_amdgcn_sched_barrier(0);
-        if constexpr (CL > 0)
-            spmm_accumulate_chunk<HB, U, RB, CL, VT, XT, AT>(m, base, G, hi, c, st, w, v, xv, buf, lane);
-        else
-            spmm_accumulate<HB, U, RB, VT, XT, AT>(m, base, G, hi, w, v, xv, buf, lane);
+        spmm_accumulate<HB, U, RB, VT, XT, AT>(m, base, G, hi, w, v, xv, buf, lane);
         if (more) {
             base = nb;
         } else {
-            spmm_finish<HB, RB, XT, AT, CL>(m, sb, s1, buf, lane);
+            spmm_finish<HB, RB, XT, AT>(m, sb, s1, buf, lane);
             sb += S;
             if (sb >= s1) break;
             s += S;
@@ -405,6 +523,63 @@ __device__ inline void spmm_tile(const SpmmMat& m, int s0, int s1, AT* __restric
             w[u] = w2[u];
             v[u] = v2[u];
         }
+    }
+}
+
+// spmm_tile with chunk lanes: groups of C = 2^CL lanes (G >= C) sharing their
+// entries, the stream data loaded C entries per lane and vector
+// (ChunkStream), each lane gathering and adding its chunk of the group's
+// entries.  Same pipelining, with two scheduling barriers fixing the order of
+// a step: the gathers, then the next step's stream loads, then the products
+// (without the first the compiler issued one gather at a time; without the
+// second it hoisted the multiplications above the stream loads, which then
+// waited for every gather).  Lane (s, e) of group g = e - c: the group's
+// entries of a step are g + u * G + j.
+template <int HB, int RB, typename VT, typename XT, typename AT, int CL>
+__device__ inline void spmm_tile_chunk(const SpmmMat& m, int s0, int s1, AT* __restrict__ buf, int lane) {
+    constexpr int U = SpmmUnroll<RB>::U;
+    constexpr int XV = static_cast<int>(16 / sizeof(XT));
+    constexpr int C = 1 << CL;
+    static_assert(U % C == 0, "whole vectors per lane");
+    const int g_log = m.g_log;
+    const int G = 1 << g_log;
+    const int S = kWave >> g_log;
+    const int e = lane & (G - 1);
+    const int c = e & (C - 1);
+    const int32_t* __restrict__ sp = m.strip_ptr;
+#pragma unroll
+    for (int i = 0; i < HB * (sizeof(AT) == 8 ? XV : RB); ++i) buf[i * kWave + lane] = AT(0);
+    int s = s0 + (lane >> g_log);
+    int lo = sp[min(s, s1)], hi = sp[min(s + 1, s1)];
+    int lo_n = sp[min(s + S, s1)], hi_n = sp[min(s + S + 1, s1)];
+    int base = lo + e;
+    const int st = min(c * XV, m.nrhs - XV);
+    ChunkStream<U, CL, VT> t;
+    spmm_load_chunk<U, CL, VT>(m, base - c, G, hi, c, t);
+    for (int sb = s0;;) {
+        XT xv[U << CL][XV];
+        spmm_gather_chunk<U, CL, VT, XT>(m, t, st, xv);
+        __builtin_amdgcn_sched_barrier(0);
+        const int nb = base + U * G;
+        const bool more = ballot(nb < hi) != 0ull;
+        ChunkStream<U, CL, VT> t2;
+        spmm_load_chunk<U, CL, VT>(m, (more ? nb : lo_n + e) - c, G, more ? hi : hi_n, c, t2);
+        __builtin_amdgcn_sched_barrier(0);
+        spmm_accumulate_chunk<HB, U, RB, CL, VT, XT, AT>(m, base - c, G, hi, c, st, t, xv, buf, lane);
+        if (more) {
+            base = nb;
+        } else {
+            spmm_finish_chunk<HB, RB, XT, AT, CL>(m, sb, s1, buf, lane);
+            sb += S;
+            if (sb >= s1) break;
+            s += S;
+            lo = lo_n;
+            hi = hi_n;
+            base = lo + e;
+            lo_n = sp[min(s + S, s1)];
+            hi_n = sp[min(s + S + 1, s1)];
+        }
+        t = t2;
     }
 }
 
@@ -479,12 +654,13 @@ __device__ inline void spmm_tile_nv(const SpmmMat& m, int s0, int s1, AT* buf, i
         return;
     } else if constexpr (!VEC) {
         spmm_tile<HB, RB, 0, VT, XT, AT>(m, s0, s1, buf, lane);
-    } else if constexpr (RB / XV >= 2) {
-        // Chunk lanes when the group has room for them (nrhs > RB / 2 >= XV
-        // here, so every chunk is one 16-byte load).
+    } else if constexpr (RB / XV >= 2 && !std::is_same<VT, bf16_t>::value) {
+        // Chunk lanes when the group has room for them and the matrix holds a
+        // whole vector of entries (nrhs > RB / 2 >= XV here, so every chunk is
+        // one 16-byte load; bf16 values, 2-byte aligned, stay on single loads).
         constexpr int CL = RB / XV >= 4 ? 2 : 1;
-        if (m.g_log >= CL) {
-            spmm_tile<HB, RB, 0, VT, XT, AT, CL>(m, s0, s1, buf, lane);
+        if (spmm_chunk_log(m, XV, false) == CL) {
+            spmm_tile_chunk<HB, RB, VT, XT, AT, CL>(m, s0, s1, buf, lane);
         } else if (m.nrhs == RB) {
             spmm_tile<HB, RB, RB / XV, VT, XT, AT>(m, s0, s1, buf, lane);
         } else {
@@ -517,7 +693,7 @@ __global__ __launch_bounds__(kSpmmMaxWaves * kWave) void spmm_kernel(SpmmMat m, 
     const long long sb = (static_cast<long long>(xcd_logical_block(blockIdx.x, gridDim.x)) * wpb + wave) * span;
     if (sb >= strips) return;
     const int s1 = static_cast<int>(std::min<long long>(strips, sb + span));
-    buf += wave * (HB * RB * kWave);
+    buf += wave * (spmm_lane_slots(m, static_cast<int>(16 / sizeof(XT)), std::is_same<VT, bf16_t>::value) * kWave);
     if constexpr (RB <= 2) {
         // One pass per wave (passes == 1), no pipelining.
 #pragma unroll
@@ -630,7 +806,8 @@ void launch_spmm_hb(const SpmmMat& m, int strips, int wpb, size_t lds, hipStream
 
 template <typename VT, typename XT, typename AT>
 hipError_t launch_spmm_typed(const SpmmMat& m, int strips, hipStream_t stream) {
-    const size_t wave_bytes = spmm_wave_lds_bytes(m.hb << m.rb_log, sizeof(AT));
+    const size_t wave_bytes = spmm_wave_lds_bytes(
+        spmm_lane_slots(m, static_cast<int>(16 / sizeof(XT)), std::is_same<VT, bf16_t>::value), sizeof(AT));
     const int wpb = spmm_waves_per_block(wave_bytes);
     const size_t lds = wave_bytes * wpb;
     switch (m.hb) {
@@ -719,7 +896,8 @@ SpmmPlanShape spmm_plan_shape(int count, const cmrs_mat_t* mats, const int* nrhs
     for (int i = 0; i < count; ++i) {
         const SpmmMat m = spmm_mat(&mats[i], nrhs[i], nullptr, nrhs[i], nullptr, nrhs[i], group);
         order.push_back({m.hb * 16 + m.rb_log, i});
-        sh.max_slots = std::max(sh.max_slots, m.hb << m.rb_log);
+        const int xv = mats[i].val_dtype == CMRS_R64F ? 2 : 4;
+        sh.max_slots = std::max(sh.max_slots, spmm_lane_slots(m, xv, mats[i].val_dtype == CMRS_R16BF));
     }
     std::stable_sort(order.begin(), order.end(),
                      [](const std::pair<int, int>& a, const std::pair<int, int>& b) { return a.first < b.first; });
