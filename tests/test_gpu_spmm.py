@@ -154,6 +154,35 @@ def test_spmm_several_passes_per_wave(C, dtype, group, nrhs, ld):
     assert np.array_equal(Yb.cpu().numpy().view(ut), Y.cpu().numpy().view(ut))
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("rows,max_row", [(3, 2), (9, 1), (37, 3), (200, 6)])
+def test_spmm_tiny_matrices_chunk_lanes(C, dtype, rows, max_row):
+    """Matrices of a handful of entries (4 or more, so chunk lanes run): most
+    of a group's vector stream loads are moved back from past the last entry
+    or lie wholly past their strip, for 3-8 right-hand sides, groups of 4 and
+    16 lanes, heights 1, 2 and 4; the batched launch gives the same bits."""
+    A = synth.random_csr(rows, 50, max_row=max_row, seed=rows)
+    if A.nnz < 4:
+        A = synth.random_csr(rows, 50, max_row=max_row + 2, seed=rows + 1, empty_row_frac=0.0)
+    assert A.nnz >= 4
+    rp, ci, v, hv = G.upload(A, dtype)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    ut = np.uint64 if dtype == "f64" else np.uint32
+    for h in (1, 2, 4):
+        M = C.from_csr(rp, ci, v, A.cols, h, sort=True)
+        for nrhs in (3, 5, 6, 8):
+            for group in (4, 16):
+                X, Xs = _rhs(A, nrhs, dtype, seed=nrhs * 7 + group)
+                Y = C.spmm(M, X, group=group)
+                torch.cuda.synchronize()
+                _check_cols(A, hv, dtype, Xs, Y.cpu().numpy().astype(np.float64))
+                Yb = torch.full((A.rows, nrhs), float("nan"), dtype=tdt, device="cuda")
+                plan = C.spmm_plan([M], [X], [Yb], group=group)
+                C.spmm_batched(plan)
+                torch.cuda.synchronize()
+                assert np.array_equal(Yb.cpu().numpy().view(ut), Y.cpu().numpy().view(ut)), (h, nrhs, group)
+
+
 def test_spmm_no_entries(C):
     A = synth.random_csr(777, 300, max_row=0, seed=1)
     assert A.nnz == 0
