@@ -192,16 +192,16 @@ __device__ inline void spmm_accumulate(const SpmmMat& m, int base, int G, int hi
 
 // Chunk lanes.  From two 16-byte chunks per row piece on (4 or 8 fp64
 // right-hand-side slots, 8 fp32 ones), each group of C = 2^CL consecutive
-// lanes (a pair or a quad) shares the work of its C lanes' entries: lane c of
-// the group gathers chunk c of every one of those C row pieces and adds the
+// lanes (a pair or a quad) shares the work of its entries: lane c of the
+// group gathers chunk c of every one of the group's row pieces and adds the
 // products for its own XV slots c * XV .. c * XV + XV - 1.  A gather
 // instruction then touches 64 / C row pieces, each read whole by C adjacent
-// lanes, instead of 64 pieces read a chunk at a time: with X in L2 such
-// gathers run ~1.45x faster for 64-byte pieces, since the vector-memory
-// address path handles each distinct line of an instruction separately.  The
-// stream loads stay one entry per lane; the C words and values of a group are
-// exchanged with DPP quad permutations (no LDS).  Lane c of a group owns
-// partial columns of the slots of chunk c only; the others stay +0.0.
+// lanes, instead of 64 pieces read a chunk at a time (with X in L2, 64-byte
+// pieces gathered that way ran ~1.45x faster in a probe).  The stream data
+// are loaded C entries per lane as vectors (ChunkStream) and exchanged
+// within the group with DPP quad permutations (no LDS).  Lane c keeps
+// partials for the slots of chunk c only: in fp64 just those (HB * XV per
+// lane, spmm_lane_slots), in fp32 within the full layout, the rest +0.0.
 
 // The value of lane `src` of this lane's group of 2^CL lanes (CL = 1: pairs
 // (0, 1), (2, 3) of each quad; CL = 2: the quad).  src must fold to a
