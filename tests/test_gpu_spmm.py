@@ -313,18 +313,23 @@ def test_batched_single_tile_per_matrix_and_empty(C):
             _check_cols(A, hv, "f64", Xh, Y.cpu().numpy())
 
 
-def test_batched_full_workload_sampled_rows(C):
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batched_full_workload_sampled_rows(C, dtype):
     """The full uneven batch (256 matrices, 10k-500k rows, 1.1e9 entries) in
-    fp64 with the default plan, one persistent launch: 16 sampled rows of
-    every matrix and every right-hand side against the oracle's row sums."""
+    fp64 and fp32 with the default plan, one persistent launch: 16 sampled
+    rows of every matrix and every right-hand side against the oracle's row
+    sums (fp32: on the fp32 values and x, with the fp32 bound)."""
     from synth import gpu_families as F
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    u = U64 if dtype == "f64" else U32
     W = F.batched_workload(seed=0)
     mats, Xs, Ys, keep = [], [], [], []
     for i, (fam, rp, ci, val, cols, r) in enumerate(W):
+        val = val.to(tdt)
         mats.append(C.from_csr(rp, ci, val, cols, 4, sort=True))
-        X = torch.randn(cols, r, dtype=torch.float64, device="cuda")
+        X = torch.randn(cols, r, dtype=torch.float64, device="cuda").to(tdt)
         Xs.append(X)
-        Ys.append(torch.full((rp.numel() - 1, r), float("nan"), dtype=torch.float64, device="cuda"))
+        Ys.append(torch.full((rp.numel() - 1, r), float("nan"), dtype=tdt, device="cuda"))
         keep.append((rp, ci, val))
     plan = C.spmm_plan(mats, Xs, Ys)
     C.spmm_batched(plan)
@@ -334,17 +339,17 @@ def test_batched_full_workload_sampled_rows(C):
         rows = rp.numel() - 1
         sample = np.unique(np.concatenate([[0, rows - 1], g.integers(0, rows, 14)]))
         hrp = rp.cpu().numpy()
-        Xh = X.cpu().numpy()
-        Yh = Y.cpu().numpy()
+        Xh = X.cpu().numpy().astype(np.float64)
+        Yh = Y.cpu().numpy().astype(np.float64)
         for i in sample:
             a, b = int(hrp[i]), int(hrp[i + 1])
             sub_rp = np.array([0, b - a], dtype=np.int32)
             cols_i = ci[a:b].cpu().numpy()
-            vals_i = val[a:b].cpu().numpy()
+            vals_i = val[a:b].cpu().numpy().astype(np.float64)
             for k in range(X.shape[1]):
                 xk = np.ascontiguousarray(Xh[:, k])
                 ref = oracle.csr_spmv(sub_rp, cols_i, vals_i, xk)[0]
-                tol = oracle.spmv_bound(sub_rp, cols_i, vals_i, xk, U64, factor=4.0)[0]
+                tol = oracle.spmv_bound(sub_rp, cols_i, vals_i, xk, u, factor=4.0)[0]
                 assert abs(Yh[i, k] - ref) <= tol, (i, k)
 
 
