@@ -307,6 +307,51 @@ __device__ inline uint32_t chunk_word(const ChunkStream<U, CL, VT>& t, int u, in
     return group_read<CL>(chunk_pick<C>(t.w[u >> CL], t.d[u >> CL], j), u & (C - 1));
 }
 
+// Stream data of one or two right-hand sides, blocked: lane e of a strip
+// takes runs of V = 4 consecutive entries, lo + V e + k V G + i (i < V), and
+// loads each run as one vector of words and one of values (a quarter of the
+// addresses of one entry per load; the vector-memory address path costs
+// about the same per lane whatever the width).  Runs are moved back from
+// past the matrix's last entry or to the strip's last entry as in
+// ChunkStream; element i is picked at min(i + d, V - 1).  Only matrices of
+// at least V entries take this path; bf16 values (2-byte aligned) do not.
+constexpr int kBlk = 4;
+
+template <int U, typename VT>
+struct BlkStream {
+    static constexpr int NV = U / kBlk;
+    typename SVec<uint32_t, kBlk>::type w[NV];
+    typename SVec<VT, kBlk>::type v[NV];
+    int d[NV];
+    __device__ uint32_t word(int u) const { return chunk_pick<kBlk>(w[u / kBlk], d[u / kBlk], u % kBlk); }
+    __device__ VT value(int u) const { return chunk_pick<kBlk>(v[u / kBlk], d[u / kBlk], u % kBlk); }
+};
+
+// Entry u of a lane's step starting at base (base = lo + V e + step U G).
+__device__ inline int blk_entry(int base, int G, int u) {
+    return base + (u / kBlk) * kBlk * G + u % kBlk;
+}
+
+template <int U, typename VT>
+__device__ inline void spmm_load_blk(const SpmmMat& m, int base, int G, int hi, BlkStream<U, VT>& t) {
+    typedef typename SVec<uint32_t, kBlk>::type WV;
+    typedef typename SVec<VT, kBlk>::type VV;
+    const VT* __restrict__ val = static_cast<const VT*>(m.val);
+#pragma unroll
+    for (int k = 0; k < BlkStream<U, VT>::NV; ++k) {
+        const int j = base + k * kBlk * G;
+        const int jv = max(min(min(j, hi - 1), m.nnz - kBlk), 0);
+        t.d[k] = j - jv;
+        t.w[k] = __builtin_nontemporal_load(reinterpret_cast<const WV*>(m.word + jv));
+        t.v[k] = __builtin_nontemporal_load(reinterpret_cast<const VV*>(val + jv));
+    }
+}
+
+template <typename VT>
+__host__ __device__ constexpr bool spmm_blk_type() {
+    return !std::is_same<VT, bf16_t>::value;
+}
+
 // Chunk c of the row pieces of the group's U * C entries: one 16-byte load
 // each, elements st .. st + XV - 1 with st = c * XV, moved back to st = nrhs
 // - XV when the chunk would reach past nrhs.  Entries past their strip's end
@@ -583,6 +628,72 @@ __device__ inline void spmm_tile_chunk(const SpmmMat& m, int s0, int s1, AT* __r
     }
 }
 
+// spmm_tile for one or two right-hand sides with blocked stream data
+// (BlkStream): the same pipelined step, each lane's entries taken in runs of
+// kBlk consecutive ones.  Sums the same products in the same order as
+// spmm_pass_small_blk, the single-launch form.
+template <int HB, int RB, typename VT, typename XT, typename AT>
+__device__ inline void spmm_tile_blk(const SpmmMat& m, int s0, int s1, AT* __restrict__ buf, int lane) {
+    constexpr int U = SpmmUnroll<RB>::U;
+    constexpr int SLOTS = HB * RB;
+    const int g_log = m.g_log;
+    const int G = 1 << g_log;
+    const int S = kWave >> g_log;
+    const int e = lane & (G - 1);
+    const uint32_t mask = (1u << m.bits) - 1u;
+    const XT* __restrict__ x = static_cast<const XT*>(m.x);
+    const size_t ldx = static_cast<size_t>(m.ldx);
+    const int last = m.nrhs - 1;
+    const int32_t* __restrict__ sp = m.strip_ptr;
+#pragma unroll
+    for (int i = 0; i < SLOTS; ++i) buf[i * kWave + lane] = AT(0);
+    int s = s0 + (lane >> g_log);
+    int lo = sp[min(s, s1)], hi = sp[min(s + 1, s1)];
+    int lo_n = sp[min(s + S, s1)], hi_n = sp[min(s + S + 1, s1)];
+    int base = lo + kBlk * e;
+    BlkStream<U, VT> t;
+    spmm_load_blk<U, VT>(m, base, G, hi, t);
+    for (int sb = s0;;) {
+        XT xv[U][RB];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const XT* xr = x + static_cast<size_t>(t.word(u) >> m.bits) * ldx;
+#pragma unroll
+            for (int k = 0; k < RB; ++k) xv[u][k] = xr[min(k, last)];
+        }
+        const int nb = base + U * G;
+        const bool more = ballot(nb < hi) != 0ull;
+        BlkStream<U, VT> t2;
+        spmm_load_blk<U, VT>(m, more ? nb : lo_n + kBlk * e, G, more ? hi : hi_n, t2);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool ok = blk_entry(base, G, u) < hi;
+            const uint32_t w = t.word(u);
+            const AT a = static_cast<AT>(t.value(u));
+            AT* slot = buf + static_cast<int>(w & mask & (HB - 1)) * RB * kWave + lane;
+#pragma unroll
+            for (int k = 0; k < RB; ++k) {
+                const AT p = a * static_cast<AT>(xv[u][k]);
+                lds_add(slot + k * kWave, ok ? p : AT(0));
+            }
+        }
+        if (more) {
+            base = nb;
+        } else {
+            spmm_finish<HB, RB, XT, AT>(m, sb, s1, buf, lane);
+            sb += S;
+            if (sb >= s1) break;
+            s += S;
+            lo = lo_n;
+            hi = hi_n;
+            base = lo + kBlk * e;
+            lo_n = sp[min(s + S, s1)];
+            hi_n = sp[min(s + S + 1, s1)];
+        }
+        t = t2;
+    }
+}
+
 // One pass over strips [sb, sb + S) (those below s_end) for one or two
 // right-hand sides, without the pipelining: a lane loads the words and values
 // of its U entries, gathers and adds only those inside its strip (branches
@@ -636,6 +747,47 @@ __device__ inline void spmm_pass_small(const SpmmMat& m, int sb, int s_end, AT* 
     spmm_finish<HB, RB, XT, AT>(m, sb, s_end, buf, lane);
 }
 
+// spmm_pass_small with blocked stream data (BlkStream): the products of the
+// same entries, added in the same order as spmm_tile_blk.
+template <int HB, int RB, typename VT, typename XT, typename AT>
+__device__ inline void spmm_pass_small_blk(const SpmmMat& m, int sb, int s_end, AT* __restrict__ buf, int lane) {
+    static_assert(RB <= 2, "one or two right-hand-side slots");
+    constexpr int U = SpmmUnroll<RB>::U;
+    const int g_log = m.g_log;
+    const int G = 1 << g_log;
+    const int e = lane & (G - 1);
+    const int s = sb + (lane >> g_log);
+    const uint32_t mask = (1u << m.bits) - 1u;
+    if (s < s_end) {
+        const int lo = m.strip_ptr[s], hi = m.strip_ptr[s + 1];
+        const XT* __restrict__ x = static_cast<const XT*>(m.x);
+        const size_t ldx = static_cast<size_t>(m.ldx);
+        for (int base = lo + kBlk * e; base < hi; base += U * G) {
+            BlkStream<U, VT> t;
+            spmm_load_blk<U, VT>(m, base, G, hi, t);
+            XT xv[U][RB];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (blk_entry(base, G, u) < hi) {
+                    const XT* xr = x + static_cast<size_t>(t.word(u) >> m.bits) * ldx;
+#pragma unroll
+                    for (int k = 0; k < RB; ++k) xv[u][k] = xr[k];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (blk_entry(base, G, u) < hi) {
+                    const AT a = static_cast<AT>(t.value(u));
+                    AT* slot = buf + static_cast<int>(t.word(u) & mask & (HB - 1)) * RB * kWave + lane;
+#pragma unroll
+                    for (int k = 0; k < RB; ++k) lds_add(slot + k * kWave, a * static_cast<AT>(xv[u][k]));
+                }
+            }
+        }
+    }
+    spmm_finish<HB, RB, XT, AT>(m, sb, s_end, buf, lane);
+}
+
 // How many 16-byte chunks of each X piece are read as vector loads: all of
 // them (those reaching past nrhs moved back to end at nrhs, NV = -1, when
 // nrhs does not fill the bucket; at least one chunk's worth of right-hand
@@ -653,6 +805,12 @@ __device__ inline void spmm_tile_nv(const SpmmMat& m, int s0, int s1, AT* buf, i
     if constexpr (static_cast<size_t>(HB) * RB * kWave * sizeof(AT) > kSpmmWaveLdsMax) {
         return;
     } else if constexpr (!VEC) {
+        if constexpr (RB <= 2 && spmm_blk_type<VT>()) {
+            if (m.nnz >= kBlk) {
+                spmm_tile_blk<HB, RB, VT, XT, AT>(m, s0, s1, buf, lane);
+                return;
+            }
+        }
         spmm_tile<HB, RB, 0, VT, XT, AT>(m, s0, s1, buf, lane);
     } else if constexpr (RB / XV >= 2 && !std::is_same<VT, bf16_t>::value) {
         // Chunk lanes when the group has room for them and the matrix holds a
@@ -698,6 +856,12 @@ __global__ __launch_bounds__(kSpmmMaxWaves * kWave) void spmm_kernel(SpmmMat m, 
         // One pass per wave (passes == 1), no pipelining.
 #pragma unroll
         for (int i = 0; i < HB * RB; ++i) buf[i * kWave + lane] = AT(0);
+        if constexpr (spmm_blk_type<VT>()) {
+            if (m.nnz >= kBlk) {
+                spmm_pass_small_blk<HB, RB, VT, XT, AT>(m, static_cast<int>(sb), s1, buf, lane);
+                return;
+            }
+        }
         spmm_pass_small<HB, RB, VT, XT, AT>(m, static_cast<int>(sb), s1, buf, lane);
     } else {
         spmm_tile_nv<HB, RB, VT, XT, AT>(m, static_cast<int>(sb), s1, buf, lane);
