@@ -18,7 +18,7 @@ import torch
 from . import cmrs
 
 DEFAULT_CANDIDATES = {
-    "tile_nnz": (8_192, 32_768, 131_072),
+    "tile_nnz": (4_096, 8_192, 32_768),
     "group": (0, 8, 16),
     "blocks_per_cu": (2, 4, 8),
 }
