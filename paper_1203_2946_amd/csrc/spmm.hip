@@ -14,7 +14,9 @@
 // are software-pipelined: each step issues the next step's stream loads
 // before adding its own products (spmm_tile).  Where a row piece spans two or
 // four 16-byte chunks, groups of adjacent lanes share their entries and each
-// lane gathers one chunk of every piece of its group (chunk lanes, below).
+// lane gathers one chunk of every piece of its group (chunk lanes, below);
+// for one or two right-hand sides a lane takes its entries in runs of four
+// consecutive ones, read as vectors (BlkStream).
 //
 // The batched path runs that body from one persistent kernel: waves take
 // work tiles (a matrix and a range of its strips) from per-XCD queue counters
