@@ -204,7 +204,7 @@ def batched_report(fixed=None):
             fixed_cfg[k] = (h_, {"tile_nnz": t_, "group": g_, "blocks_per_cu": b_})
     for dt, tdt in (("f64", torch.float64), ("f32", torch.float32)):
         best = None
-        for h in ((fixed_cfg[dt][0],) if dt in fixed_cfg else (2, 4)):
+        for h in ((fixed_cfg[dt][0],) if dt in fixed_cfg else (2, 4, 8)):
             mats, Xs, Ys, nr = [], [], [], []
             for fam, rp, ci, val, cols, r in W:
                 mats.append(cmrs.from_csr(rp, ci, val.to(tdt), cols, h, sort=True))
